@@ -1,0 +1,266 @@
+"""Pins for the FP64 oracle: closed forms, special values, invariants, brute
+force and a library zgemm -- none of which reuse the oracle's own code.
+
+Each test names the passage of "GPU-Powered Coherent Beamforming" it rests on.
+A plausible slip in the oracle (sign of the phase, missing 2*pi or c0,
+conjugated weights, transposed operand, dropped imaginary cross term, wrong
+window indexing) fails at least one of them; ``test_planted_mistakes``
+checks that claim by planting such slips in a Python twin of the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4907_amd import synth
+
+C0 = 299_792_458.0
+
+
+def plane_wave(pos, k, f, s):
+    """x[t][n] = s[t] * exp(+2 pi i f (k . r_n) / c0): a wavefront from k
+    (Sec. 1); written from the geometry, not from the oracle."""
+    tau = (pos @ k) / C0                      # arrival-time offset per antenna
+    return s[:, None] * np.exp(2j * np.pi * f * tau)[None, :]
+
+
+# --- weights: special values of the Eq. 1 phase model (Sec. 1) -------------
+
+def test_weight_special_values():
+    f = 400e6
+    lam = C0 / f
+    k = np.array([[0.0, 0.0, 1.0]])
+    # antenna at the origin, a quarter, half, full wavelength along k
+    pos = np.array([[0, 0, 0], [0, 0, lam / 4], [0, 0, lam / 2], [0, 0, lam]], dtype=float)
+    w = oracle.weights(pos, k, [f])[0, 0]
+    np.testing.assert_allclose(w, [1, -1j, -1, 1], atol=1e-12)
+    # a position orthogonal to the pointing gets no phase
+    w2 = oracle.weights(np.array([[123.0, 0, 0]]), k, [f])[0, 0, 0]
+    assert abs(w2 - 1) < 1e-15
+
+
+def test_weight_modulus_and_frequency_scaling():
+    g = np.random.default_rng(1)
+    pos = g.uniform(-300, 300, (17, 3))
+    dirs = synth.random_dirs(5, g)
+    f = np.array([100e6, 200e6])
+    w = oracle.weights(pos, dirs, f)
+    np.testing.assert_allclose(np.abs(w), 1.0, atol=1e-14)
+    # phase is linear in f: W(2f) = W(f)^2
+    np.testing.assert_allclose(w[1], w[0] ** 2, atol=1e-10)
+
+
+# --- P1: on-beam plane wave gives I * N^2 * |s|^2 ----------------------------
+
+@pytest.mark.parametrize("I", [1, 4])
+def test_on_beam_plane_wave(I):
+    w = synth.paper()
+    f = w.freqs[[0, 511, 1023]]
+    k = w.dirs[37]
+    T = 64
+    g = np.random.default_rng(2)
+    s = 5.0 * np.exp(1j * g.uniform(0, 2 * np.pi, T))       # |s| = 5
+    x = np.stack([plane_wave(w.pos, k, fc, s) for fc in f])
+    W = oracle.weights(w.pos, k[None, :], f)
+    P = oracle.beamform(W, x, I)
+    N = w.pos.shape[0]
+    np.testing.assert_allclose(P, I * N * N * 25.0, rtol=1e-12)
+
+
+def test_on_beam_quantised_bound():
+    """int8 rounding moves each antenna sample by at most sqrt(2)/2, so
+    |B - N s| <= N sqrt(2)/2 on the steered beam."""
+    w = synth.small()
+    T = 256
+    s = 40.0 * np.exp(2j * np.pi * 0.013 * np.arange(T))
+    xc = plane_wave(w.pos, w.dirs[0], w.freqs[5], s)
+    xq = np.stack([np.rint(xc.real), np.rint(xc.imag)], -1).astype(np.int8)[None]
+    W = oracle.weights(w.pos, w.dirs[:1], w.freqs[5:6])
+    P = oracle.beamform(W, xq, 1)[0, 0]
+    N = 32
+    amp = np.sqrt(P)
+    assert np.all(np.abs(amp - N * 40.0) <= N * math.sqrt(2) / 2 + 1e-9)
+
+
+# --- P2: off-source response = array factor of Eq. 1 -------------------------
+
+def test_off_source_line_array_dirichlet():
+    N, d, f = 32, 10.0, 408e6
+    pos = synth.line_positions(N, d)
+    ts, tb = 7.0, -3.0
+    k_s = synth.dir_from_xz_angle([ts])[0]
+    k_b = synth.dir_from_xz_angle([tb, ts + 0.05, 20.0])
+    T = 8
+    s = np.full(T, 3.0 + 0j)
+    x = plane_wave(pos, k_s, f, s)[None]
+    P = oracle.beamform(oracle.weights(pos, k_b, [f]), x, 1)[0]
+    for b, th in enumerate([tb, ts + 0.05, 20.0]):
+        psi = 2 * np.pi * f * d * (math.sin(math.radians(ts)) - math.sin(math.radians(th))) / C0
+        af = (math.sin(N * psi / 2) / math.sin(psi / 2)) ** 2
+        np.testing.assert_allclose(P[b], 9.0 * af, rtol=1e-9, atol=1e-9)
+
+
+def test_off_source_grid_product_of_dirichlets():
+    nx, ny, dx, dy, f = 4, 8, 10.0, 20.0, 408e6
+    pos = synth.grid_positions(nx, ny, dx, dy)
+    k_s = synth.dir_from_lm_angles([4.0], [-6.0])[0]
+    k_b = synth.dir_from_lm_angles([1.0, -10.0], [2.0, 9.0])
+    x = plane_wave(pos, k_s, f, np.ones(4, dtype=complex))[None]
+    P = oracle.beamform(oracle.weights(pos, k_b, [f]), x, 1)[0]
+
+    def dir2(n, psi):
+        return (math.sin(n * psi / 2) / math.sin(psi / 2)) ** 2
+
+    for b in range(2):
+        px = 2 * np.pi * f * dx * (k_s[0] - k_b[b, 0]) / C0
+        py = 2 * np.pi * f * dy * (k_s[1] - k_b[b, 1]) / C0
+        np.testing.assert_allclose(P[b], dir2(nx, px) * dir2(ny, py), rtol=1e-9)
+
+
+# --- P3: a single live antenna -----------------------------------------------
+
+def test_single_live_antenna():
+    w = synth.small()
+    g = np.random.default_rng(3)
+    x = np.zeros((2, 16, 32, 2), dtype=np.int8)
+    x[:, :, 9, :] = g.integers(-128, 128, (2, 16, 2))
+    W = oracle.weights(w.pos, w.dirs, w.freqs[:2])
+    P = oracle.beamform(W, x, 1)
+    ref = (x[:, :, 9, 0].astype(float) ** 2 + x[:, :, 9, 1].astype(float) ** 2)
+    np.testing.assert_allclose(P, np.broadcast_to(ref[:, None, :], P.shape), rtol=1e-13)
+
+
+# --- P4: linearity seen through the power ------------------------------------
+
+def test_linearity_scaling_and_parallelogram():
+    w = synth.small()
+    g = np.random.default_rng(4)
+    X = g.integers(-63, 64, (2, 32, 32, 2)).astype(np.int8)
+    Y = g.integers(-63, 64, (2, 32, 32, 2)).astype(np.int8)
+    W = oracle.weights(w.pos, w.dirs, w.freqs[:2])
+    P = lambda v: oracle.beamform(W, v, 4)  # noqa: E731
+    np.testing.assert_allclose(P((2 * X).astype(np.int8)), 4 * P(X), rtol=1e-12)
+    lhs = P((X + Y).astype(np.int8)) + P((X - Y).astype(np.int8))
+    np.testing.assert_allclose(lhs, 2 * P(X) + 2 * P(Y), rtol=1e-11)
+
+
+# --- P5: brute force with Python complex numbers -----------------------------
+
+def test_brute_force_tiny():
+    g = np.random.default_rng(5)
+    for N, C, B, T, I in [(1, 1, 1, 1, 1), (3, 2, 3, 8, 2), (4, 2, 2, 6, 3), (2, 1, 3, 8, 8)]:
+        pos = g.uniform(-50, 50, (N, 3))
+        dirs = synth.random_dirs(B, g)
+        freqs = g.uniform(300e6, 500e6, C)
+        x = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+        P = oracle.beamform(oracle.weights(pos, dirs, freqs), x, I)
+        for c in range(C):
+            for b in range(B):
+                for wdw in range(T // I):
+                    acc = 0.0
+                    for t in range(wdw * I, wdw * I + I):
+                        beam = 0j
+                        for n in range(N):
+                            delay = sum(dirs[b][j] * pos[n][j] for j in range(3)) / C0
+                            wt = complex(math.cos(2 * math.pi * freqs[c] * delay),
+                                         -math.sin(2 * math.pi * freqs[c] * delay))
+                            beam += wt * complex(int(x[c, t, n, 0]), int(x[c, t, n, 1]))
+                        acc += abs(beam) ** 2
+                    assert abs(P[c, b, wdw] - acc) <= 1e-12 * max(1.0, acc)
+
+
+# --- P6: per-channel zgemm from numpy ----------------------------------------
+
+def test_numpy_zgemm():
+    w = synth.small()
+    x = w.voltages(channels=[0, 77], n_samples=512)
+    W = oracle.weights(w.pos, w.dirs, w.freqs[[0, 77]])
+    P = oracle.beamform(W, x, 8)
+    xc = x[..., 0].astype(float) + 1j * x[..., 1]
+    for c in range(2):
+        beams = xc[c] @ W[c].T                       # [T][B]
+        ref = (np.abs(beams) ** 2).reshape(64, 8, -1).sum(1).T
+        np.testing.assert_allclose(P[c], ref, rtol=1e-12)
+
+
+# --- P7: DFT weights and Parseval --------------------------------------------
+
+def test_dft_parseval():
+    N = 16
+    n = np.arange(N)
+    W = np.exp(-2j * np.pi * np.outer(n, n) / N)[None]       # raw weights, B = N
+    g = np.random.default_rng(7)
+    x = g.integers(-128, 128, (1, 20, N, 2)).astype(np.int8)
+    P = oracle.beamform(W, x, 1)[0]                           # [B][T]
+    energy = (x[0].astype(np.int64) ** 2).sum(axis=(1, 2))    # integer
+    np.testing.assert_allclose(P.sum(axis=0), N * energy, rtol=1e-13)
+
+
+def test_dft_single_bin():
+    """X = exp(+2 pi i k0 n / N) lands entirely in DFT beam k0 with power N^2."""
+    N, k0 = 8, 3
+    n = np.arange(N)
+    W = np.exp(-2j * np.pi * np.outer(n, n) / N)[None]
+    x = np.exp(2j * np.pi * k0 * n / N)[None, None, :]
+    P = oracle.beamform(W, x, 1)[0, :, 0]
+    ref = np.zeros(N)
+    ref[k0] = N * N
+    np.testing.assert_allclose(P, ref, atol=1e-11)
+
+
+# --- P9-P11: invariances -----------------------------------------------------
+
+def test_translation_permutation_conjugation():
+    w = synth.small()
+    x = w.voltages(channels=[3, 4], n_samples=64)
+    f = w.freqs[3:5]
+    P = oracle.beamform(oracle.weights(w.pos, w.dirs, f), x, 2)
+    # P9: shifting every antenna by the same vector changes each beam by a
+    # common phase only
+    Pt = oracle.beamform(oracle.weights(w.pos + np.array([13.0, -7.0, 2.5]), w.dirs, f), x, 2)
+    np.testing.assert_allclose(Pt, P, rtol=1e-10)
+    # P10: permuting antennas in positions and voltages together
+    perm = np.random.default_rng(10).permutation(32)
+    Pp = oracle.beamform(oracle.weights(w.pos[perm], w.dirs, f), np.ascontiguousarray(x[:, :, perm]), 2)
+    np.testing.assert_allclose(Pp, P, rtol=1e-10)
+    # P11: conjugated voltages seen by the opposite pointing
+    xc = x.copy()
+    xc[..., 1] = -x[..., 1]
+    Pc = oracle.beamform(oracle.weights(w.pos, -w.dirs, f), xc, 2)
+    np.testing.assert_allclose(Pc, P, rtol=1e-10)
+
+
+# --- P12: independence of channels and beams ---------------------------------
+
+def test_channel_and_beam_independence():
+    w = synth.small()
+    x = w.voltages(channels=[0, 1, 2], n_samples=64)
+    W = oracle.weights(w.pos, w.dirs, w.freqs[:3])
+    P = oracle.beamform(W, x, 1)
+    x2 = x.copy()
+    x2[1] = -x2[1] // 2
+    W2 = W.copy()
+    W2[:, 2] *= 1j
+    P2 = oracle.beamform(W2, x2, 1)
+    assert np.array_equal(P2[[0, 2]][:, [0, 1, 3]], P[[0, 2]][:, [0, 1, 3]])
+
+
+# --- integration windows -----------------------------------------------------
+
+@pytest.mark.parametrize("I", [1, 2, 3, 16, 64])
+def test_integration_windows(I):
+    w = synth.small()
+    x = w.voltages(channels=[9], n_samples=192)
+    W = oracle.weights(w.pos, w.dirs, w.freqs[9:10])
+    P1 = oracle.beamform(W, x, 1)
+    PI = oracle.beamform(W, x, I)
+    np.testing.assert_allclose(PI, P1.reshape(1, 4, -1, I).sum(-1), rtol=1e-13)
+
+
+def test_rejects_bad_args():
+    W = np.ones((1, 1, 2), dtype=complex)
+    with pytest.raises(ValueError):
+        oracle.beamform(W, np.zeros((1, 10, 2, 2), np.int8), 3)
+    with pytest.raises(ValueError):
+        oracle.beamform(W, np.zeros((1, 10, 3, 2), np.int8), 1)
