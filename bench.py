@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 coherent beamformer on one GPU.
+
+One step = one bf_run over one synthetic block of the paper-scale workload
+(BEST-2-like 4x8 array, 1024 channels over 16 MHz at 408 MHz, 128 beams,
+65536 samples, integration 16), i.e. the whole hot path: int8 voltages in
+HBM -> per-channel complex GEMM on MFMA -> |B|^2 -> integration -> FP32
+power in HBM.  Inputs are resident in HBM before timing starts.  Prints one
+JSON line (see ``main``).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--precision fp32|fp16|bf16] [--workload paper|small|precision]
+                       [--no-cpu-baseline] [--no-extra]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "fp16": 2516.6, "bf16": 2516.6}  # MI355X dense MFMA
+PEAK_HBM_GBS = 8000.0
+DTYPE = {"fp32": "f32", "fp16": "f16 (f32 accumulate)", "bf16": "bf16 (f32 accumulate)"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "small", "precision"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other-precision legs")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_1412_4907_amd import synth
+    return {"paper": synth.paper, "small": synth.small, "precision": synth.precision}[name]()
+
+
+def algorithmic_bytes(w, prec) -> float:
+    """Bytes one launch must move at minimum: every voltage once, every
+    weight once, every output window once."""
+    es = 4 if prec == "fp32" else 2
+    x = w.n_chan * w.n_samples * w.n_ant * 2
+    wt = w.n_chan * w.n_beams * w.n_ant * 2 * es
+    p = w.n_chan * w.n_beams * (w.n_samples // w.integration) * 4
+    return float(x + wt + p)
+
+
+def time_plan(plan, xd, p, steps, warmup, torch):
+    """Per-step HIP events on torch's current stream (the stream bf_run is
+    given); returns per-step ms and the whole timed region in ms."""
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    xp, pp = xd.data_ptr(), p.data_ptr()
+    for _ in range(warmup):
+        plan.run_ptr(xp, pp, sp)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        plan.run_ptr(xp, pp, sp)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    total = ev[0].elapsed_time(ev[steps])
+    return per, total
+
+
+def cpu_baseline(w, budget_s: float) -> dict:
+    """The FP64 oracle, as it stands, on a bounded channel sample of the same
+    workload (all beams, all samples of each sampled channel)."""
+    import oracle
+    g = np.random.default_rng(4907)
+    order = g.permutation(w.n_chan)
+    W = oracle.weights(w.pos, w.dirs, w.freqs[order[:1]])
+    x1 = w.voltages(channels=order[:1])
+    t = time.perf_counter()
+    oracle.beamform(W, x1, w.integration)
+    t1 = time.perf_counter() - t
+    n = int(max(1, min(w.n_chan - 1, budget_s / max(t1, 1e-3))))
+    chans = order[1:1 + n]
+    W = oracle.weights(w.pos, w.dirs, w.freqs[chans])
+    x = w.voltages(channels=chans, workers=8)
+    t = time.perf_counter()
+    oracle.beamform(W, x, w.integration)
+    dt = time.perf_counter() - t
+    flops = 8.0 * len(chans) * w.n_beams * w.n_samples * w.n_ant
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{len(chans)} of {w.n_chan} channels (seeded), all {w.n_beams} beams x "
+                      f"{w.n_samples} samples x {w.n_ant} antennas, I={w.integration}; "
+                      f"{dt:.1f} s FP64 on the host"}
+
+
+def load_traffic(kernel_key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel build (else null)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    e = d.get(kernel_key)
+    if not e:
+        return None
+    from paper_1412_4907_amd import build as pbuild
+    if e.get("source_hash") != pbuild.source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(channel-sharded multi-GPU operation is a design note only)"}))
+        sys.exit(2)
+    import torch
+    from paper_1412_4907_amd import bf
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = workload(a.workload)
+    t0 = time.perf_counter()
+    x = w.voltages(workers=16)
+    gen_s = time.perf_counter() - t0
+    xd = torch.from_numpy(x).to(dev)
+    del x
+    windows = w.n_samples // w.integration
+
+    def leg(prec, steps, warmup):
+        plan = bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration, precision=prec)
+        plan.set_weights(w.pos, w.dirs, w.freqs)
+        p = torch.empty((w.n_chan, w.n_beams, windows), dtype=torch.float32, device=dev)
+        per, total = time_plan(plan, xd, p, steps, warmup, torch)
+        info = plan.info()
+        plan.destroy()
+        del p
+        return per, total, info
+
+    per, total, info = leg(a.precision, a.steps, a.warmup)
+    ms = total / a.steps
+    flops = w.flops
+    value = flops / (ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[a.precision]
+    abytes = algorithmic_bytes(w, a.precision)
+    chan_rate = 16e6 / 1024  # channel sample rate of every workload here
+    block_s = w.n_samples / chan_rate
+    kernel_key = f"beamform/{w.name}/{a.precision}"
+    out = {
+        "metric": "beamforming TFLOP/s (8 flop/cMAC) + % MFMA peak; real-time factor, p99 block ms",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[a.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: N={w.n_ant} antennas, C={w.n_chan} channels, "
+                               f"B={w.n_beams} beams, T={w.n_samples} samples, I={w.integration}",
+                   "precision": a.precision, "n_antennas": w.n_ant, "n_channels": w.n_chan,
+                   "n_beams": w.n_beams, "n_samples": w.n_samples, "integration": w.integration,
+                   "tile": [info["tile_mt"], info["tile_nbt"], info["tile_nbp"],
+                            info["sg_per_wave"]],
+                   "work_units": info["work_units"]},
+        "mfma_peak_frac": round(value / peak, 4),
+        "real_time_factor": round(block_s / (ms * 1e-3), 1),
+        "p50_block_ms": round(float(np.percentile(per, 50)), 4),
+        "p99_block_ms": round(float(np.percentile(per, 99)), 4),
+        "block_period_ms": round(block_s * 1e3, 3),
+        "roofline": {"bound": "mfma", "achieved": round(value, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(value / peak, 4),
+                     "traffic": load_traffic(kernel_key),
+                     "algorithmic_bytes": abytes,
+                     "algorithmic_hbm_gbs": round(abytes / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(abytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "input_gen_s": round(gen_s, 1),
+    }
+    if not a.no_extra:
+        extra = {}
+        for prec in ("fp32", "fp16", "bf16"):
+            if prec == a.precision:
+                continue
+            per2, total2, _ = leg(prec, a.steps, a.warmup)
+            ms2 = total2 / a.steps
+            v2 = flops / (ms2 * 1e-3) / 1e12
+            ab2 = algorithmic_bytes(w, prec)
+            extra[prec] = {"tflops": round(v2, 3), "ms_per_step": round(ms2, 4),
+                           "mfma_peak_frac": round(v2 / PEAK_TFLOPS[prec], 4),
+                           "hbm_frac": round(ab2 / (ms2 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                           "p99_block_ms": round(float(np.percentile(per2, 99)), 4)}
+        out["other_precisions"] = extra
+    del xd
+    if not a.no_cpu_baseline:
+        cb = cpu_baseline(w, a.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["gpu_over_cpu"] = round(value / cb["value"], 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

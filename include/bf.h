@@ -1,0 +1,196 @@
+/*
+ * bf.h -- C ABI of the MI355X (gfx950) coherent beamformer.
+ *
+ * The library forms, for every frequency channel c, time sample t and beam b,
+ *
+ *     B[c][b][t]  = sum_n W[c][b][n] * X[c][t][n]                (Sec. 2.1)
+ *     W[c][b][n]  = exp(-i 2 pi f_c (k_b . r_n) / c0)             (Eq. 1, Sec. 1)
+ *     P[c][b][w]  = sum_{j<I} |B[c][b][w*I + j]|^2                (Sec. 2.1)
+ *
+ * i.e. a per-channel complex matrix product (beams x antennas times
+ * antennas x samples; Sec. 2.1 describes it as an N_b x N_a coefficient
+ * matrix applied to each antenna vector), with power detection and
+ * integration over I consecutive samples fused into the same kernel so that
+ * complex beams never reach device memory (Sec. 2.1 argues for fusing
+ * unpacking, conversion and power into the beamformer).  Throughput is
+ * counted at 8 flop per complex multiply-accumulate (Sec. 2.2).
+ *
+ * Conventions
+ *   - Antenna positions r_n in metres (x = East, y = North, z = up), beam
+ *     pointings k_b unit vectors toward the sky, channel centre frequencies
+ *     f_c in Hz, c0 = 299792458 m/s.  A plane wave from k_s reaches antenna n
+ *     as s(t) exp(+i 2 pi f (k_s . r_n) / c0), so a beam with k_b = k_s sums
+ *     it in phase (power N^2 |s|^2).
+ *   - Voltages X: device memory, int8 two's complement, layout
+ *     [C][T][N][2] = (re, im) interleaved, antenna fastest.  Every value in
+ *     [-128, 127] is accepted and converted exactly.
+ *   - Output P: device memory, float32, layout [C][B][T/I].
+ *   - Non-overlapping integration windows, aligned at t = 0; T % I == 0.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the legacy
+ *     default stream).  All device work is asynchronous and stream-ordered;
+ *     a call that returns BF_OK has only enqueued work.  Device faults
+ *     surface at the caller's next synchronisation.
+ *   - Every entry point returns a status (BF_OK or a negative BF_ERR_*)
+ *     and never throws or aborts.  A plan or batch is not thread-safe;
+ *     distinct handles are.
+ *
+ * Precision forms
+ *   BF_FP32  weights rounded from FP64 to FP32; int8 voltages converted to
+ *            FP32; products on FP32 matrix cores (MFMA), FP32 accumulation.
+ *   BF_FP16  weights rounded from FP64 to FP16 (round to nearest even, one
+ *            rounding); voltages converted exactly to FP16; FP16 MFMA with
+ *            FP32 accumulation.
+ *   BF_BF16  as BF_FP16 with BF16 weights and BF16 MFMA.
+ *   In every form the weight phase f_c (k_b . r_n) / c0 (in cycles) is
+ *   computed and reduced modulo 1 in FP64 on the device before sin/cos.
+ */
+#ifndef BF_H
+#define BF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bf_plan_s* bf_plan_t;
+typedef struct bf_batch_s* bf_batch_t;
+
+typedef enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2 } bf_precision_t;
+
+enum {
+  BF_OK = 0,
+  BF_ERR_INVALID_ARG = -1, /* bad size, null or misaligned pointer, bad value   */
+  BF_ERR_OOM = -2,         /* device or pinned-host allocation failed             */
+  BF_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed          */
+  BF_ERR_STATE = -4,       /* e.g. bf_run before any weights were set             */
+  BF_ERR_UNSUPPORTED = -5  /* valid request outside what this build implements    */
+};
+
+/* Plan flags. */
+#define BF_ACCUMULATE 1u /* bf_run adds into P instead of overwriting it, so an
+                            integration window can span several blocks        */
+
+/* Human-readable text for a status code (static storage, never NULL). */
+const char* bf_strerror(int status);
+
+/* Version string of the library build (static storage). */
+const char* bf_version(void);
+
+/* Name and text of the last HIP error this thread's calls into the library
+ * turned into BF_ERR_HIP / BF_ERR_OOM ("no error" if none).  Thread-local
+ * storage, valid until the thread's next failing call. */
+const char* bf_last_hip_error(void);
+
+/*
+ * Create a plan for N antennas, C channels, B beams, T samples per block and
+ * integration I (all >= 1, T % I == 0, N <= 4096, B <= 65536, C <= 2^24).
+ * bf_plan_create makes an FP32 plan with no flags.  The plan allocates its
+ * device weight buffer (C * ceil(B/16)*16 * 2 * K rows, K = 64*ceil(N/32),
+ * in the storage precision) on the current device and a small pinned host
+ * staging area.  On success *out owns them until bf_plan_destroy.
+ * Errors: BF_ERR_INVALID_ARG (sizes, null out, unknown precision or flags),
+ * BF_ERR_OOM, BF_ERR_HIP.  *out is set to NULL on failure.
+ */
+int bf_plan_create(bf_plan_t* out, int32_t n_antennas, int32_t n_channels, int32_t n_beams,
+                   int64_t n_samples, int32_t integration);
+int bf_plan_create_ex(bf_plan_t* out, int32_t n_antennas, int32_t n_channels, int32_t n_beams,
+                      int64_t n_samples, int32_t integration, bf_precision_t precision,
+                      uint32_t flags);
+
+/*
+ * Generate the plan's weights on the device from geometry (Eq. 1 phase
+ * model, Sec. 1; Sec. 3.2 recomputes them whenever pointings change):
+ *   ant_xyz_m    host [N][3] double, metres
+ *   beam_dir     host [B][3] double, unit vectors (|norm - 1| <= 1e-9)
+ *   chan_freq_hz host [C]    double, Hz, finite and > 0
+ * The host arrays are copied before return; the caller may free them at
+ * once.  The phase is evaluated in FP64, reduced modulo one cycle, and each
+ * weight component is rounded once to the storage precision.
+ * Errors: BF_ERR_INVALID_ARG (null pointer, non-finite value, non-unit
+ * direction, non-positive frequency), BF_ERR_HIP.
+ */
+int bf_set_weights(bf_plan_t plan, const double* ant_xyz_m, const double* beam_dir,
+                   const double* chan_freq_hz, void* stream);
+
+/*
+ * Load arbitrary complex weights (host [C][B][N][2] double, re/im), each
+ * component rounded once to the storage precision.  Synchronous (returns
+ * after the device copy is complete).  Used for DFT/integer-weight tests
+ * and for weights computed elsewhere.
+ * Errors: BF_ERR_INVALID_ARG (null, non-finite), BF_ERR_OOM, BF_ERR_HIP.
+ */
+int bf_set_weights_raw(bf_plan_t plan, const double* weights, void* stream);
+
+/*
+ * Copy the plan's rounded weights back to host [C][B][N][2] double.
+ * Synchronous.  Errors: BF_ERR_INVALID_ARG, BF_ERR_STATE (none set),
+ * BF_ERR_HIP.
+ */
+int bf_get_weights(bf_plan_t plan, double* weights_out, void* stream);
+
+/*
+ * The hot path: one block.  x_dev: device int8 [C][T][N][2]; p_dev: device
+ * float [C][B][T/I]; both 16-byte aligned and not overlapping.  Enqueues
+ * one kernel on `stream`; no host synchronisation, no allocation.
+ * Errors: BF_ERR_INVALID_ARG (null or misaligned pointer), BF_ERR_STATE
+ * (weights never set), BF_ERR_HIP (launch failure).
+ */
+int bf_run(bf_plan_t plan, const int8_t* x_dev, float* p_dev, void* stream);
+
+/* Plan introspection (tile choice and sizes), filled by bf_plan_info. */
+typedef struct {
+  int32_t n_antennas, n_channels, n_beams, integration;
+  int64_t n_samples;
+  int32_t precision;      /* bf_precision_t                                     */
+  int32_t k_padded;       /* 2N rounded up to a multiple of 64                  */
+  int32_t beams_padded;   /* B rounded up to a multiple of 16                   */
+  int32_t tile_mt;        /* 16-sample MFMA row tiles per wave step             */
+  int32_t tile_nbt;       /* 16-beam tiles per workgroup                        */
+  int32_t tile_nbp;       /* 16-beam tiles per accumulator pass                 */
+  int32_t sg_per_wave;    /* 16-window store groups per wave per work unit      */
+  int64_t work_units;     /* workgroups of one bf_run                           */
+  int64_t weight_bytes;   /* device bytes of the weight buffer                  */
+  int64_t lds_bytes;      /* LDS per workgroup                                  */
+  double flops;           /* 8 * C * B * T * N                                  */
+} bf_plan_info_t;
+int bf_plan_info(bf_plan_t plan, bf_plan_info_t* info);
+
+/*
+ * Override the plan's tile choice (used by the autotuner).  mt in {4, 8},
+ * nbt in {1, 2, 4, 8}, nbp in {1, 2, 4} with nbp <= nbt, sg_per_wave >= 1.
+ * A combination this build does not instantiate returns BF_ERR_UNSUPPORTED
+ * and leaves the plan unchanged.
+ */
+int bf_plan_set_tile(bf_plan_t plan, int32_t mt, int32_t nbt, int32_t nbp, int32_t sg_per_wave);
+
+/* Free the plan.  Waits for the plan's outstanding device work first.
+ * NULL is accepted (no-op). */
+int bf_plan_destroy(bf_plan_t plan);
+
+/*
+ * Batching form: several independent plans (sub-arrays or beam sets of
+ * uneven N, C, B, T; Sec. 1 mentions partitioning an array into independent
+ * phased sub-arrays) run in one persistent launch: a grid sized to the
+ * device whose workgroups take work units from a device queue spanning all
+ * sets.  All plans must share precision and integration class (I == 1,
+ * I == 2, or I >= 3) and have their weights set; up to 16 plans.  The batch
+ * references the plans (they must outlive it) and owns a device queue
+ * counter.
+ * Errors: BF_ERR_INVALID_ARG, BF_ERR_UNSUPPORTED, BF_ERR_OOM, BF_ERR_HIP.
+ */
+int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n_plans);
+
+/* x_dev[i], p_dev[i]: host arrays of device pointers, one per plan, same
+ * layout and alignment rules as bf_run.  One launch on `stream` (after a
+ * one-thread queue reset kernel).  Each set's output is bitwise identical to
+ * bf_run of that plan alone. */
+int bf_batch_run(bf_batch_t batch, const int8_t* const* x_dev, float* const* p_dev, void* stream);
+
+int bf_batch_destroy(bf_batch_t batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BF_H */

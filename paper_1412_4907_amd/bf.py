@@ -1,0 +1,241 @@
+"""Thin Python binding of the gfx950 beamformer C ABI (``include/bf.h``).
+
+Argument marshalling only: every step of the beamforming path runs in the
+HIP kernels of ``libbf.so``.  PyTorch supplies device memory (tensors passed
+by ``data_ptr()``) and streams (``torch.cuda.Stream.cuda_stream``).  If the
+library has not been built, every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbf.so")
+
+FP32, FP16, BF16 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "fp16": FP16, "bf16": BF16}
+ACCUMULATE = 1
+
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+# every entry point declared in include/bf.h
+EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_plan_create", "bf_plan_create_ex", "bf_set_weights",
+           "bf_set_weights_raw", "bf_get_weights", "bf_run", "bf_plan_info", "bf_plan_set_tile",
+           "bf_plan_destroy", "bf_batch_create", "bf_batch_run", "bf_batch_destroy"]
+
+
+class BfError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        detail = ""
+        if status in (ERR_HIP, ERR_OOM):
+            detail = " [" + lib().bf_last_hip_error().decode() + "]"
+        super().__init__(f"{where}: {strerror(status)} ({status}){detail}")
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_antennas", ctypes.c_int32), ("n_channels", ctypes.c_int32),
+                ("n_beams", ctypes.c_int32), ("integration", ctypes.c_int32),
+                ("n_samples", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("k_padded", ctypes.c_int32), ("beams_padded", ctypes.c_int32),
+                ("tile_mt", ctypes.c_int32), ("tile_nbt", ctypes.c_int32),
+                ("tile_nbp", ctypes.c_int32), ("sg_per_wave", ctypes.c_int32),
+                ("work_units", ctypes.c_int64), ("weight_bytes", ctypes.c_int64),
+                ("lds_bytes", ctypes.c_int64), ("flops", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libbf.so (built in-tree by ``paper_1412_4907_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(python -m paper_1412_4907_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        L.bf_strerror.restype = ctypes.c_char_p
+        L.bf_strerror.argtypes = [ctypes.c_int]
+        L.bf_version.restype = ctypes.c_char_p
+        L.bf_last_hip_error.restype = ctypes.c_char_p
+        L.bf_plan_create.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32]
+        L.bf_plan_create_ex.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, ctypes.c_int, u32]
+        L.bf_set_weights.argtypes = [P, P, P, P, P]
+        L.bf_set_weights_raw.argtypes = [P, P, P]
+        L.bf_get_weights.argtypes = [P, P, P]
+        L.bf_run.argtypes = [P, P, P, P]
+        L.bf_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
+        L.bf_plan_set_tile.argtypes = [P, i32, i32, i32, i32]
+        L.bf_plan_destroy.argtypes = [P]
+        L.bf_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), i32]
+        L.bf_batch_run.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
+        L.bf_batch_destroy.argtypes = [P]
+        for name in EXPORTS[3:]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().bf_strerror(int(status)).decode()
+
+
+def version() -> str:
+    return lib().bf_version().decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        raise BfError(status, where)
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _host_f64(a, shape) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {a.shape}")
+    return a
+
+
+class Plan:
+    """One beam set: N antennas, C channels, B beams, T samples per block,
+    integration I.  Owns the device weights (see ``bf_plan_create_ex``)."""
+
+    def __init__(self, n_antennas: int, n_channels: int, n_beams: int, n_samples: int,
+                 integration: int = 1, precision: str | int = "fp32",
+                 accumulate: bool = False):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        _check(lib().bf_plan_create_ex(ctypes.byref(h), n_antennas, n_channels, n_beams,
+                                       n_samples, integration, prec,
+                                       ACCUMULATE if accumulate else 0), "bf_plan_create_ex")
+        self._h = h
+        self.N, self.C, self.B, self.T, self.I = (n_antennas, n_channels, n_beams, n_samples,
+                                                  integration)
+        self.precision = prec
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise ValueError("plan destroyed")
+        return self._h
+
+    @property
+    def windows(self) -> int:
+        return self.T // self.I
+
+    def set_weights(self, pos, dirs, freqs, stream=None) -> None:
+        pos = _host_f64(pos, (self.N, 3))
+        dirs = _host_f64(dirs, (self.B, 3))
+        freqs = _host_f64(freqs, (self.C,))
+        _check(lib().bf_set_weights(self.handle, pos.ctypes.data, dirs.ctypes.data,
+                                    freqs.ctypes.data, _stream_ptr(stream)), "bf_set_weights")
+
+    def set_weights_raw(self, w, stream=None) -> None:
+        w = np.asarray(w)
+        if np.iscomplexobj(w):
+            w = np.stack([w.real, w.imag], axis=-1)
+        w = _host_f64(w, (self.C, self.B, self.N, 2))
+        _check(lib().bf_set_weights_raw(self.handle, w.ctypes.data, _stream_ptr(stream)),
+               "bf_set_weights_raw")
+
+    def get_weights(self, stream=None) -> np.ndarray:
+        out = np.empty((self.C, self.B, self.N, 2), dtype=np.float64)
+        _check(lib().bf_get_weights(self.handle, out.ctypes.data, _stream_ptr(stream)),
+               "bf_get_weights")
+        return out[..., 0] + 1j * out[..., 1]
+
+    def check_io(self, x, p) -> None:
+        import torch
+        if x.dtype != torch.int8 or tuple(x.shape) != (self.C, self.T, self.N, 2):
+            raise ValueError(f"x must be int8 [{self.C}][{self.T}][{self.N}][2], "
+                             f"got {x.dtype} {tuple(x.shape)}")
+        if p.dtype != torch.float32 or tuple(p.shape) != (self.C, self.B, self.windows):
+            raise ValueError(f"p must be float32 [{self.C}][{self.B}][{self.windows}], "
+                             f"got {p.dtype} {tuple(p.shape)}")
+        for t in (x, p):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("x and p must be contiguous device tensors")
+
+    def run(self, x, p, stream=None) -> None:
+        """Enqueue one block: x int8 [C][T][N][2] -> p float32 [C][B][T/I]."""
+        self.check_io(x, p)
+        _check(lib().bf_run(self.handle, x.data_ptr(), p.data_ptr(), _stream_ptr(stream)),
+               "bf_run")
+
+    def run_ptr(self, x_ptr: int, p_ptr: int, stream_ptr: int) -> None:
+        """Same as ``run`` on raw device pointers (no checks beyond the C ABI's)."""
+        _check(lib().bf_run(self.handle, x_ptr, p_ptr, stream_ptr), "bf_run")
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        _check(lib().bf_plan_info(self.handle, ctypes.byref(i)), "bf_plan_info")
+        return i.as_dict()
+
+    def set_tile(self, mt: int, nbt: int, nbp: int, sg_per_wave: int) -> None:
+        _check(lib().bf_plan_set_tile(self.handle, mt, nbt, nbp, sg_per_wave), "bf_plan_set_tile")
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().bf_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several plans in one persistent launch (``bf_batch_create``)."""
+
+    def __init__(self, plans: Sequence[Plan]):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().bf_batch_create(ctypes.byref(h), arr, len(self.plans)), "bf_batch_create")
+        self._h = h
+
+    def run(self, xs, ps, stream=None) -> None:
+        if len(xs) != len(self.plans) or len(ps) != len(self.plans):
+            raise ValueError("one x and one p per plan")
+        for pl, x, p in zip(self.plans, xs, ps):
+            pl.check_io(x, p)
+        xa = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        pa = (ctypes.c_void_p * len(ps))(*[p.data_ptr() for p in ps])
+        _check(lib().bf_batch_run(self._h, xa, pa, _stream_ptr(stream)), "bf_batch_run")
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().bf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

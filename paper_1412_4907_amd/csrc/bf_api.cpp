@@ -1,0 +1,548 @@
+// bf_api.cpp -- host runtime of the beamformer: plans, validation, tile
+// choice, weight upload, launches and the batching form.  Every entry point
+// is extern "C", returns a status code and never lets an exception escape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/bf.h"
+#include "bf_internal.h"
+
+using bf::Launch;
+using bf::Prob;
+using bf::Tile;
+
+struct bf_plan_s {
+  int32_t N = 0, C = 0, B = 0, I = 0;
+  int64_t T = 0;
+  int prec = 0;
+  uint32_t flags = 0;
+  int32_t Bpad = 0, Kpad = 0;
+  int mode = 0;
+  bool vec16 = true;
+  Tile tile{4, 1, 1};
+  int32_t sgw = 1;
+  int device = 0;
+  int n_cu = 256;
+  size_t w_bytes = 0;
+  void* w_dev = nullptr;
+  bool weights_set = false;
+  // geometry staging for bf_set_weights: pinned host + device, reused
+  double* geo_host = nullptr;
+  double* geo_dev = nullptr;
+  size_t geo_count = 0;
+  hipEvent_t geo_done = nullptr;
+  bool geo_pending = false;
+};
+
+struct bf_batch_s {
+  std::vector<bf_plan_t> plans;
+  int32_t* queue = nullptr;
+  int device = 0;
+};
+
+namespace {
+
+constexpr int kMaxN = 4096;
+constexpr int kMaxB = 65536;
+constexpr int kMaxC = 1 << 24;
+constexpr size_t kLdsMax = 160 * 1024 - 256;  // dynamic LDS; the rest is static
+
+int es_of(int prec) { return prec == BF_FP32 ? 4 : 2; }
+
+size_t lds_bytes(int prec, int Kpad, int nbt) {
+  return (size_t)2 * 16 * nbt * ((size_t)Kpad * es_of(prec) + bf::kLdsPad);
+}
+
+int mode_of(int32_t I) { return I == 1 ? bf::kModeI1 : (I == 2 ? bf::kModeI2 : bf::kModeGen); }
+
+// Geometry of the row-tile schedule for integration I (see bf_beamform.inc).
+void schedule(int32_t I, int64_t T, int32_t* G, int32_t* QI, int32_t* SG) {
+  int64_t W = T / I;
+  if (I == 1) {
+    *G = 1;
+    *QI = 1;
+  } else if (I == 2) {
+    *G = 2;
+    *QI = 1;
+  } else {
+    *QI = (I + 3) / 4;
+    *G = 4 * *QI;
+  }
+  *SG = (int32_t)((W + 15) / 16);
+}
+
+int gcd(int a, int b) { return b ? gcd(b, a % b) : a; }
+
+bool tile_exists(bool vec16, Tile t) {
+  static const Tile vec[] = {{4, 8, 2}, {8, 8, 2}, {4, 4, 4}, {8, 4, 2}, {4, 2, 2}, {4, 1, 1}};
+  static const Tile gen[] = {{4, 8, 2}, {4, 1, 1}};
+  const Tile* list = vec16 ? vec : gen;
+  int n = vec16 ? 6 : 2;
+  for (int i = 0; i < n; ++i)
+    if (list[i].mt == t.mt && list[i].nbt == t.nbt && list[i].nbp == t.nbp) return true;
+  return false;
+}
+
+// Work units per bf_run for a tile/sgw choice.
+int64_t units_for(const bf_plan_s* p, Tile t, int32_t sgw) {
+  int32_t G, QI, SG;
+  schedule(p->I, p->T, &G, &QI, &SG);
+  int64_t nbr = (p->Bpad / 16 + t.nbt - 1) / t.nbt;
+  int64_t ntr = (SG + (int64_t)bf::kWaves * sgw - 1) / ((int64_t)bf::kWaves * sgw);
+  return (int64_t)p->C * nbr * ntr;
+}
+
+// Default tile: the largest beam tile whose weight slice fits 80 KB of LDS
+// (two workgroups per CU), MT = 8 on FP16/BF16 (more MFMA per fragment
+// load), then enough store groups per wave that a launch has >= 8
+// workgroups per CU without exceeding 256 row tiles per wave per unit.
+void choose_tile(bf_plan_s* p) {
+  const int need = (p->Bpad / 16);
+  Tile t{4, 1, 1};
+  if (!p->vec16) {
+    t = (need >= 4 && lds_bytes(p->prec, p->Kpad, 8) <= 80 * 1024) ? Tile{4, 8, 2} : Tile{4, 1, 1};
+  } else {
+    int nbt = 8;
+    while (nbt > 1 && (lds_bytes(p->prec, p->Kpad, nbt) > 80 * 1024 || nbt / 2 >= need)) nbt /= 2;
+    if (p->prec == BF_FP32) {
+      t = nbt == 8 ? Tile{4, 8, 2} : nbt == 4 ? Tile{4, 4, 4} : nbt == 2 ? Tile{4, 2, 2} : Tile{4, 1, 1};
+    } else {
+      t = nbt == 8 ? Tile{8, 8, 2} : nbt == 4 ? Tile{8, 4, 2} : nbt == 2 ? Tile{4, 2, 2} : Tile{4, 1, 1};
+    }
+  }
+  int32_t G, QI, SG;
+  schedule(p->I, p->T, &G, &QI, &SG);
+  const int32_t base = t.mt / gcd(t.mt, G);  // sgw * G must be a multiple of MT
+  int32_t sgw = base;
+  const int64_t want = (int64_t)p->n_cu * 8;
+  for (int32_t k = 2;; ++k) {
+    int32_t s = base * k;
+    if ((int64_t)s * G > 256 || units_for(p, t, s) < want) break;
+    if ((int64_t)(s - base) * bf::kWaves >= SG) break;
+    sgw = s;
+  }
+  p->tile = t;
+  p->sgw = sgw;
+}
+
+Prob make_prob(const bf_plan_s* p, const int8_t* x, float* out, int64_t unit_begin) {
+  Prob q;
+  std::memset(&q, 0, sizeof(q));
+  q.x = x;
+  q.p = out;
+  q.w = p->w_dev;
+  q.T = p->T;
+  q.W = p->T / p->I;
+  q.unit_begin = unit_begin;
+  q.N = p->N;
+  q.C = p->C;
+  q.B = p->B;
+  q.I = p->I;
+  q.Bpad = p->Bpad;
+  q.Kpad = p->Kpad;
+  int32_t G, QI, SG;
+  schedule(p->I, p->T, &G, &QI, &SG);
+  q.G = G;
+  q.QI = QI;
+  q.SG = SG;
+  q.sgw = p->sgw;
+  q.nbr = (p->Bpad / 16 + p->tile.nbt - 1) / p->tile.nbt;
+  q.ntr = (int32_t)((SG + (int64_t)bf::kWaves * p->sgw - 1) / ((int64_t)bf::kWaves * p->sgw));
+  q.accumulate = (p->flags & BF_ACCUMULATE) ? 1 : 0;
+  return q;
+}
+
+thread_local char g_last_error[256] = "no error";
+
+int from_hip(hipError_t e) {
+  if (e == hipSuccess) return BF_OK;
+  (void)hipGetLastError();  // the status is returned; do not leave it pending for others
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s (%d): %s", hipGetErrorName(e), (int)e,
+                hipGetErrorString(e));
+  if (e == hipErrorOutOfMemory) return BF_ERR_OOM;
+  return BF_ERR_HIP;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* bf_strerror(int status) {
+  switch (status) {
+    case BF_OK: return "success";
+    case BF_ERR_INVALID_ARG: return "invalid argument";
+    case BF_ERR_OOM: return "out of memory";
+    case BF_ERR_HIP: return "HIP runtime error";
+    case BF_ERR_STATE: return "invalid state (weights not set?)";
+    case BF_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+const char* bf_version(void) { return "bf 0.1 gfx950"; }
+
+const char* bf_last_hip_error(void) { return g_last_error; }
+
+int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T, int32_t I,
+                      bf_precision_t precision, uint32_t flags) {
+  try {
+    if (!out) return BF_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (N < 1 || N > kMaxN || C < 1 || C > kMaxC || B < 1 || B > kMaxB || T < 1 || I < 1 ||
+        T % I != 0 || T > ((int64_t)1 << 40))
+      return BF_ERR_INVALID_ARG;
+    if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
+      return BF_ERR_INVALID_ARG;
+    if (flags & ~BF_ACCUMULATE) return BF_ERR_INVALID_ARG;
+    bf_plan_s* p = new (std::nothrow) bf_plan_s();
+    if (!p) return BF_ERR_OOM;
+    p->N = N;
+    p->C = C;
+    p->B = B;
+    p->T = T;
+    p->I = I;
+    p->prec = precision;
+    p->flags = flags;
+    p->Bpad = (B + 15) / 16 * 16;
+    p->Kpad = (2 * N + bf::kChunk - 1) / bf::kChunk * bf::kChunk;
+    p->mode = mode_of(I);
+    p->vec16 = (2 * N) % 16 == 0;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return BF_ERR_HIP;
+    }
+    hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (p->n_cu < 1) p->n_cu = 256;
+    if (lds_bytes(p->prec, p->Kpad, 1) > kLdsMax) {
+      delete p;
+      return BF_ERR_UNSUPPORTED;
+    }
+    choose_tile(p);
+    p->w_bytes = (size_t)C * p->Bpad * 2 * p->Kpad * es_of(p->prec);
+    hipError_t e = hipMalloc(&p->w_dev, p->w_bytes);
+    if (e != hipSuccess) {
+      delete p;
+      return from_hip(e);
+    }
+    e = hipMemset(p->w_dev, 0, p->w_bytes);
+    p->geo_count = (size_t)3 * N + (size_t)3 * B + (size_t)C;
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->geo_host, p->geo_count * sizeof(double), 0);
+    if (e == hipSuccess) e = hipMalloc(&p->geo_dev, p->geo_count * sizeof(double));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->geo_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      bf_plan_destroy(p);
+      return from_hip(e);
+    }
+    *out = p;
+    return BF_OK;
+  } catch (...) {
+    return BF_ERR_OOM;
+  }
+}
+
+int bf_plan_create(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T, int32_t I) {
+  return bf_plan_create_ex(out, N, C, B, T, I, BF_FP32, 0u);
+}
+
+int bf_plan_destroy(bf_plan_t p) {
+  if (!p) return BF_OK;
+  try {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipSetDevice(p->device);
+    hipDeviceSynchronize();
+    if (p->w_dev) hipFree(p->w_dev);
+    if (p->geo_dev) hipFree(p->geo_dev);
+    if (p->geo_host) hipHostFree(p->geo_host);
+    if (p->geo_done) hipEventDestroy(p->geo_done);
+    hipSetDevice(dev);
+    delete p;
+    return BF_OK;
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
+int bf_set_weights(bf_plan_t p, const double* pos, const double* dir, const double* freq,
+                   void* stream) {
+  try {
+    if (!p || !pos || !dir || !freq) return BF_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < 3 * (int64_t)p->N; ++i)
+      if (!std::isfinite(pos[i])) return BF_ERR_INVALID_ARG;
+    for (int b = 0; b < p->B; ++b) {
+      const double* d = dir + 3 * b;
+      if (!std::isfinite(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2]))
+        return BF_ERR_INVALID_ARG;
+      double nrm = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (std::fabs(nrm - 1.0) > 1e-9) return BF_ERR_INVALID_ARG;
+    }
+    for (int c = 0; c < p->C; ++c)
+      if (!std::isfinite(freq[c]) || !(freq[c] > 0.0)) return BF_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // the previous upload must have left the pinned staging area
+    if (p->geo_pending) {
+      hipError_t e = hipEventSynchronize(p->geo_done);
+      if (e != hipSuccess) return from_hip(e);
+      p->geo_pending = false;
+    }
+    double* h = p->geo_host;
+    std::memcpy(h, pos, sizeof(double) * 3 * p->N);
+    std::memcpy(h + 3 * p->N, dir, sizeof(double) * 3 * p->B);
+    std::memcpy(h + 3 * p->N + 3 * p->B, freq, sizeof(double) * p->C);
+    hipError_t e = hipMemcpyAsync(p->geo_dev, h, p->geo_count * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return from_hip(e);
+    e = hipEventRecord(p->geo_done, s);
+    if (e != hipSuccess) return from_hip(e);
+    p->geo_pending = true;
+    const double* d = p->geo_dev;
+    e = bf::launch_weights_geom(p->prec, d, d + 3 * p->N, d + 3 * p->N + 3 * p->B, p->N, p->C,
+                                p->B, p->Bpad, p->Kpad, p->w_dev, s);
+    if (e != hipSuccess) return from_hip(e);
+    p->weights_set = true;
+    return BF_OK;
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
+int bf_set_weights_raw(bf_plan_t p, const double* w, void* stream) {
+  try {
+    if (!p || !w) return BF_ERR_INVALID_ARG;
+    const size_t n = (size_t)p->C * p->B * p->N * 2;
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(w[i])) return BF_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    double* dw = nullptr;
+    hipError_t e = hipMalloc(&dw, n * sizeof(double));
+    if (e != hipSuccess) return from_hip(e);
+    e = hipMemcpyAsync(dw, w, n * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = bf::launch_weights_raw(p->prec, dw, p->N, p->C, p->B, p->Bpad, p->Kpad, p->w_dev, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    hipFree(dw);
+    if (e != hipSuccess) return from_hip(e);
+    if (e2 != hipSuccess) return from_hip(e2);
+    p->weights_set = true;
+    return BF_OK;
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
+int bf_get_weights(bf_plan_t p, double* out, void* stream) {
+  try {
+    if (!p || !out) return BF_ERR_INVALID_ARG;
+    if (!p->weights_set) return BF_ERR_STATE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::vector<uint8_t> buf(p->w_bytes);
+    hipError_t e = hipMemcpyAsync(buf.data(), p->w_dev, p->w_bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return from_hip(e);
+    auto val = [&](size_t idx) -> double {
+      if (p->prec == BF_FP32) {
+        float f;
+        std::memcpy(&f, buf.data() + idx * 4, 4);
+        return f;
+      }
+      uint16_t h;
+      std::memcpy(&h, buf.data() + idx * 2, 2);
+      if (p->prec == BF_BF16) {
+        uint32_t u = (uint32_t)h << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+      }
+      // binary16 -> double
+      int sgn = h >> 15, ex = (h >> 10) & 31, man = h & 1023;
+      double v = ex == 0 ? std::ldexp((double)man, -24)
+                         : ex == 31 ? (man ? NAN : INFINITY) : std::ldexp(1024.0 + man, ex - 25);
+      return sgn ? -v : v;
+    };
+    for (int64_t c = 0; c < p->C; ++c)
+      for (int64_t b = 0; b < p->B; ++b) {
+        size_t row = ((size_t)c * p->Bpad + b) * 2 * p->Kpad;  // re-row
+        for (int64_t n = 0; n < p->N; ++n) {
+          double* o = out + ((c * p->B + b) * p->N + n) * 2;
+          o[0] = val(row + 2 * n);
+          o[1] = -val(row + 2 * n + 1);
+        }
+      }
+    return BF_OK;
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
+int bf_run(bf_plan_t p, const int8_t* x, float* out, void* stream) {
+  try {
+    if (!p || !x || !out || !aligned16(x) || !aligned16(out)) return BF_ERR_INVALID_ARG;
+    if (!p->weights_set) return BF_ERR_STATE;
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    L.prob[0] = make_prob(p, x, out, 0);
+    L.nprob = 1;
+    L.total_units = units_for(p, p->tile, p->sgw);
+    L.queue = nullptr;
+    L.xcd_remap = 1;
+    const int64_t grid = (L.total_units + 7) / 8 * 8;
+    if (grid > 0x7FFFFFFF) return BF_ERR_UNSUPPORTED;
+    hipError_t e = bf::launch_beamform(p->prec, p->mode, p->vec16, p->tile, L, (int)grid,
+                                       lds_bytes(p->prec, p->Kpad, p->tile.nbt),
+                                       reinterpret_cast<hipStream_t>(stream));
+    return from_hip(e);
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
+int bf_plan_info(bf_plan_t p, bf_plan_info_t* info) {
+  if (!p || !info) return BF_ERR_INVALID_ARG;
+  std::memset(info, 0, sizeof(*info));
+  info->n_antennas = p->N;
+  info->n_channels = p->C;
+  info->n_beams = p->B;
+  info->integration = p->I;
+  info->n_samples = p->T;
+  info->precision = p->prec;
+  info->k_padded = p->Kpad;
+  info->beams_padded = p->Bpad;
+  info->tile_mt = p->tile.mt;
+  info->tile_nbt = p->tile.nbt;
+  info->tile_nbp = p->tile.nbp;
+  info->sg_per_wave = p->sgw;
+  info->work_units = units_for(p, p->tile, p->sgw);
+  info->weight_bytes = (int64_t)p->w_bytes;
+  info->lds_bytes = (int64_t)lds_bytes(p->prec, p->Kpad, p->tile.nbt);
+  info->flops = 8.0 * p->C * (double)p->B * (double)p->T * p->N;
+  return BF_OK;
+}
+
+int bf_plan_set_tile(bf_plan_t p, int32_t mt, int32_t nbt, int32_t nbp, int32_t sgw) {
+  if (!p || sgw < 1) return BF_ERR_INVALID_ARG;
+  Tile t{mt, nbt, nbp};
+  if (!tile_exists(p->vec16, t)) return BF_ERR_UNSUPPORTED;
+  if (lds_bytes(p->prec, p->Kpad, nbt) > kLdsMax) return BF_ERR_UNSUPPORTED;
+  int32_t G, QI, SG;
+  schedule(p->I, p->T, &G, &QI, &SG);
+  if (((int64_t)sgw * G) % mt != 0) return BF_ERR_INVALID_ARG;
+  p->tile = t;
+  p->sgw = sgw;
+  return BF_OK;
+}
+
+int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n) {
+  try {
+    if (!out) return BF_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!plans || n < 1) return BF_ERR_INVALID_ARG;
+    if (n > bf::kMaxProbs) return BF_ERR_UNSUPPORTED;
+    for (int i = 0; i < n; ++i) {
+      if (!plans[i]) return BF_ERR_INVALID_ARG;
+      if (!plans[i]->weights_set) return BF_ERR_STATE;
+      const bf_plan_s* a = plans[0];
+      const bf_plan_s* b = plans[i];
+      if (b->prec != a->prec || b->mode != a->mode || b->vec16 != a->vec16 ||
+          b->device != a->device)
+        return BF_ERR_UNSUPPORTED;
+    }
+    bf_batch_s* bt = new bf_batch_s();
+    bt->plans.assign(plans, plans + n);
+    bt->device = plans[0]->device;
+    hipError_t e = hipMalloc((void**)&bt->queue, sizeof(int32_t));
+    if (e != hipSuccess) {
+      delete bt;
+      return from_hip(e);
+    }
+    *out = bt;
+    return BF_OK;
+  } catch (...) {
+    return BF_ERR_OOM;
+  }
+}
+
+int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void* stream) {
+  try {
+    if (!bt || !x || !out) return BF_ERR_INVALID_ARG;
+    const int n = (int)bt->plans.size();
+    // One kernel instantiation serves the whole launch: the tile with the
+    // smallest beam range among the sets' own choices, which every set's
+    // LDS budget admits.  The numerics do not depend on the tile (same K
+    // order, same window sums), so each set's result equals its solo run.
+    Tile t = bt->plans[0]->tile;
+    for (int i = 0; i < n; ++i) {
+      const bf_plan_s* p = bt->plans[i];
+      if (!x[i] || !out[i] || !aligned16(x[i]) || !aligned16(out[i])) return BF_ERR_INVALID_ARG;
+      if (!p->weights_set) return BF_ERR_STATE;
+      if (p->tile.nbt < t.nbt || (p->tile.nbt == t.nbt && p->tile.mt < t.mt)) t = p->tile;
+    }
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    int64_t begin = 0;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+      bf_plan_s tmp = *bt->plans[i];  // the same set under the launch-wide tile
+      int32_t G, QI, SG;
+      schedule(tmp.I, tmp.T, &G, &QI, &SG);
+      const int32_t base = t.mt / gcd(t.mt, G);
+      tmp.tile = t;
+      tmp.sgw = std::max(base, tmp.sgw / base * base);
+      L.prob[i] = make_prob(&tmp, x[i], out[i], begin);
+      begin += units_for(&tmp, t, tmp.sgw);
+      lds = std::max(lds, lds_bytes(tmp.prec, tmp.Kpad, t.nbt));
+    }
+    if (lds > kLdsMax) return BF_ERR_UNSUPPORTED;
+    L.nprob = n;
+    L.total_units = begin;
+    L.queue = bt->queue;
+    L.xcd_remap = 0;
+    const bf_plan_s* p0 = bt->plans[0];
+    const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+    int64_t grid = std::min<int64_t>(begin, (int64_t)p0->n_cu * per_cu);
+    if (grid < 1) grid = 1;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = bf::launch_queue_reset(bt->queue, s);
+    if (e == hipSuccess)
+      e = bf::launch_beamform(p0->prec, p0->mode, p0->vec16, t, L, (int)grid, lds, s);
+    return from_hip(e);
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
+int bf_batch_destroy(bf_batch_t bt) {
+  if (!bt) return BF_OK;
+  hipDeviceSynchronize();
+  if (bt->queue) hipFree(bt->queue);
+  delete bt;
+  return BF_OK;
+}
+
+}  // extern "C"
+
+namespace bf {
+
+template <int PREC>
+hipError_t launch_prec(int mode, bool vec16, Tile t, const Launch& L, int grid, size_t lds,
+                       hipStream_t s);
+extern template hipError_t launch_prec<0>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
+extern template hipError_t launch_prec<1>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
+extern template hipError_t launch_prec<2>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
+
+hipError_t launch_beamform(int prec, int mode, bool vec16, Tile tile, const Launch& L, int grid,
+                           size_t lds_bytes, hipStream_t stream) {
+  if (prec == 0) return launch_prec<0>(mode, vec16, tile, L, grid, lds_bytes, stream);
+  if (prec == 1) return launch_prec<1>(mode, vec16, tile, L, grid, lds_bytes, stream);
+  return launch_prec<2>(mode, vec16, tile, L, grid, lds_bytes, stream);
+}
+
+}  // namespace bf

@@ -1,0 +1,7 @@
+// Beamform kernel instantiations for one storage precision (f16).
+#include "bf_internal.h"
+#include "bf_beamform.inc"
+
+namespace bf {
+template hipError_t launch_prec<1>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
+}

@@ -1,0 +1,69 @@
+// bf_internal.h -- types shared by the host runtime and the gfx950 kernels
+// of the beamformer library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bf {
+
+constexpr int kMaxProbs = 16;   // beam sets per launch (kernel-argument table)
+constexpr int kWaves = 4;       // waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr int kChunk = 64;      // real K elements (32 antennas) per chunk
+constexpr int kLdsPad = 16;     // bytes added to each LDS weight row
+
+// Integration classes; each is a separate kernel instantiation.
+enum Mode : int { kModeI1 = 0, kModeI2 = 1, kModeGen = 2 };
+
+// One beam set (plan) inside a launch.  Lives in the kernel-argument
+// segment, so every field is read through scalar loads.
+struct Prob {
+  const int8_t* x;    // [C][T][N][2] int8
+  float* p;           // [C][B][W] float
+  const void* w;      // [C][Bpad][2][Kpad] storage precision (operand layout)
+  int64_t T;          // samples per block
+  int64_t W;          // windows = T / I
+  int64_t unit_begin; // first work unit of this set in the launch
+  int32_t N, C, B, I;
+  int32_t Bpad;       // B rounded up to 16
+  int32_t Kpad;       // 2N rounded up to kChunk
+  int32_t nbr;        // beam ranges (workgroup beam slices) per channel
+  int32_t ntr;        // time ranges (work units) per channel per beam range
+  int32_t sgw;        // 16-window store groups per wave per work unit
+  int32_t G;          // MFMA row tiles per store group
+  int32_t QI;         // MFMA row tiles per window (general mode)
+  int32_t SG;         // store groups per channel
+  int32_t accumulate; // add into P instead of overwriting
+  int32_t pad_;
+};
+
+struct Launch {
+  Prob prob[kMaxProbs];
+  int64_t total_units;
+  int32_t* queue;     // persistent mode: device counter (zeroed before launch); else null
+  int32_t nprob;
+  int32_t xcd_remap;  // non-persistent mode: group consecutive units per XCD
+};
+
+// Tile variant of the beamform kernel.
+struct Tile {
+  int mt;   // 16-row MFMA tiles per wave step
+  int nbt;  // 16-beam tiles per workgroup beam range
+  int nbp;  // 16-beam tiles per accumulator pass
+};
+
+// Host-side launcher for one (precision, mode, vec16, tile) instantiation.
+// Returns hipSuccess or the launch error.
+hipError_t launch_beamform(int prec, int mode, bool vec16, Tile tile, const Launch& L,
+                           int grid, size_t lds_bytes, hipStream_t stream);
+bool tile_supported(int prec, Tile tile);
+
+hipError_t launch_weights_geom(int prec, const double* pos, const double* dir,
+                               const double* freq, int N, int C, int B, int Bpad, int Kpad,
+                               void* w, hipStream_t stream);
+hipError_t launch_weights_raw(int prec, const double* wraw, int N, int C, int B, int Bpad,
+                              int Kpad, void* w, hipStream_t stream);
+hipError_t launch_queue_reset(int32_t* q, hipStream_t stream);
+
+}  // namespace bf

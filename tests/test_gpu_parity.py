@@ -1,0 +1,225 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances (power, per-beam normwise and element-wise with near-null
+samples scaled by their beam's mean power): FP32 path 1e-5, FP16 path 2e-3
+(the stated targets); BF16 is measured against 1e-2 (its 8-bit significand
+puts weight rounding alone near 2e-3).  Integer-exact inputs must match
+bit for bit in every precision.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4907_amd import bf, synth
+from tests.gpu_util import assert_parity, round_to, run_plan
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp32": 1e-5, "fp16": 2e-3, "bf16": 1e-2}
+
+
+def _announce(msg):
+    print(msg, flush=True)
+
+
+# --- weights ---------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_weights_match_rounded_oracle(gpu, prec):
+    _announce(f"weights {prec}")
+    g = np.random.default_rng(11)
+    cases = [synth.small(),
+             synth.Workload("wide", 0, 48, 8, 37, 16, 1, synth.disc_positions(48, 250.0, g),
+                            synth.random_dirs(37, g), np.linspace(400e6, 416e6, 8))]
+    for w in cases:
+        plan = bf.Plan(w.n_ant, w.n_chan, w.n_beams, 16, 1, precision=prec)
+        plan.set_weights(w.pos, w.dirs, w.freqs)
+        got = plan.get_weights()
+        ref = round_to(oracle.weights(w.pos, w.dirs, w.freqs), prec)
+        ulp = {"fp32": 2.0 ** -23, "fp16": 2.0 ** -10, "bf16": 2.0 ** -7}[prec]
+        d = np.maximum(np.abs(got.real - ref.real), np.abs(got.imag - ref.imag))
+        # at most one unit in the last place (phase rounding of ~1e-12 rad can
+        # move a value across a rounding boundary), and almost always equal
+        assert d.max() <= ulp, (prec, d.max())
+        assert np.mean(d == 0) > 0.999, (prec, np.mean(d == 0))
+        plan.destroy()
+
+
+# --- the small configuration, full size -------------------------------------
+
+def test_small_fp32_full(gpu):
+    _announce("small fp32 full")
+    w = synth.small()
+    x = w.voltages()
+    with bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration) as plan:
+        plan.set_weights(w.pos, w.dirs, w.freqs)
+        got = run_plan(plan, x, gpu)
+    ref = oracle.beamform(oracle.weights(w.pos, w.dirs, w.freqs), x, 1)
+    st = assert_parity(got, ref, TOL["fp32"], "small fp32")
+    _announce(f"  {st}")
+    # beam 0 is steered at the tone: mean power N^2 |s|^2 + N * 2 sigma^2
+    # (coherent tone plus incoherent noise) = 32^2 * 32^2 + 32 * 512
+    expect = 32 ** 2 * 32 ** 2 + 32 * 2 * 16 ** 2
+    assert abs(got[:, 0].mean() / expect - 1) < 0.02
+
+
+# --- precision forms (512 beams) --------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_precision_forms(gpu, prec):
+    _announce(f"precision form {prec}")
+    w = synth.precision()
+    chans = [0, 17, 64, 101, 127]
+    x = w.voltages()
+    with bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, 1, precision=prec) as plan:
+        plan.set_weights(w.pos, w.dirs, w.freqs)
+        got = run_plan(plan, x, gpu)[chans]
+        wq = plan.get_weights()[chans]
+    W64 = oracle.weights(w.pos, w.dirs, w.freqs[chans])
+    ref = oracle.beamform(W64, x[chans], 1)
+    st = assert_parity(got, ref, TOL[prec], f"precision {prec}")
+    _announce(f"  vs FP64 oracle: {st}")
+    # with the same rounded weights only FP32 accumulation differs
+    ref_q = oracle.beamform(wq, x[chans], 1)
+    st_q = assert_parity(got, ref_q, 1e-5, f"precision {prec} (rounded weights)")
+    _announce(f"  vs oracle on the rounded weights: {st_q}")
+
+
+# --- paper scale, full size, sampled channels ---------------------------------
+
+@pytest.mark.slow
+def test_paper_scale_sampled(gpu):
+    import torch
+    _announce("paper scale fp32 (4.29 GB input)")
+    w = synth.paper()
+    x = w.voltages(workers=16)
+    chans = [0, 511, 1023] + list(synth.rng("paper", "check").choice(1024, 2, replace=False))
+    with bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration) as plan:
+        plan.set_weights(w.pos, w.dirs, w.freqs)
+        xd = torch.from_numpy(x).to(gpu)
+        p = torch.empty((w.n_chan, w.n_beams, w.n_samples // w.integration),
+                        dtype=torch.float32, device=gpu)
+        plan.run(xd, p)
+        torch.cuda.synchronize()
+        got = p[chans].cpu().numpy()
+        del xd, p
+    ref = oracle.beamform(oracle.weights(w.pos, w.dirs, w.freqs[chans]), x[chans], w.integration)
+    st = assert_parity(got, ref, TOL["fp32"], "paper fp32")
+    _announce(f"  {st}")
+
+
+# --- ragged and odd shapes ---------------------------------------------------
+
+RAGGED = [  # N, C, B, T, I
+    (1, 2, 1, 16, 1), (3, 3, 5, 48, 3), (5, 2, 17, 80, 5), (17, 2, 33, 96, 2),
+    (33, 1, 20, 100, 4), (8, 2, 7, 200, 8), (16, 3, 16, 1024, 16), (32, 2, 130, 1040, 16),
+    (64, 2, 40, 4096, 64), (40, 1, 9, 3000, 1), (128, 1, 24, 512, 2), (256, 1, 20, 256, 16),
+    (24, 2, 50, 1344, 7), (32, 1, 3, 17, 17), (2, 1, 2, 12, 12),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("shape", RAGGED, ids=[f"N{s[0]}C{s[1]}B{s[2]}T{s[3]}I{s[4]}" for s in RAGGED])
+def test_ragged_shapes(gpu, shape, prec):
+    N, C, B, T, I = shape
+    _announce(f"ragged {shape} {prec}")
+    g = np.random.default_rng(hash(shape) & 0xFFFF)
+    pos = synth.disc_positions(N, 200.0, g)
+    dirs = synth.random_dirs(B, g)
+    freqs = np.linspace(400e6, 416e6, C)
+    x = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+    with bf.Plan(N, C, B, T, I, precision=prec) as plan:
+        plan.set_weights(pos, dirs, freqs)
+        got = run_plan(plan, x, gpu)
+    ref = oracle.beamform(oracle.weights(pos, dirs, freqs), x, I)
+    assert_parity(got, ref, TOL[prec], f"{shape} {prec}")
+
+
+# --- integer-exact weights: bit-exact in every precision ------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_integer_exact_bitwise(gpu, prec):
+    _announce(f"integer exact {prec}")
+    g = np.random.default_rng(8)
+    N, C, B, T, I = 32, 3, 40, 512, 16
+    units = np.array([1, -1, 1j, -1j])
+    W = units[g.integers(0, 4, (C, B, N))]
+    x = g.integers(-7, 8, (C, T, N, 2)).astype(np.int8)
+    with bf.Plan(N, C, B, T, I, precision=prec) as plan:
+        plan.set_weights_raw(W)
+        got = run_plan(plan, x, gpu)
+    ref = oracle.beamform(W, x, I)
+    assert np.array_equal(got.astype(np.float64), ref)
+
+
+# --- determinism, tile invariance ---------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_deterministic_and_tile_invariant(gpu, prec):
+    _announce(f"tile invariance {prec}")
+    g = np.random.default_rng(9)
+    N, C, B, T, I = 32, 2, 128, 4096, 16
+    pos = synth.grid_positions(4, 8, 10.0, 20.0)
+    dirs = synth.random_dirs(B, g)
+    freqs = np.array([401e6, 415e6])
+    x = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+    with bf.Plan(N, C, B, T, I, precision=prec) as plan:
+        plan.set_weights(pos, dirs, freqs)
+        base = run_plan(plan, x, gpu)
+        assert np.array_equal(base, run_plan(plan, x, gpu))
+        for tile in [(4, 8, 2, 1), (8, 8, 2, 2), (4, 4, 4, 1), (8, 4, 2, 1), (4, 2, 2, 3),
+                     (4, 1, 1, 1)]:
+            plan.set_tile(*tile)
+            assert np.array_equal(base, run_plan(plan, x, gpu)), tile
+
+
+# --- integration across blocks -------------------------------------------------
+
+def test_accumulate_flag(gpu):
+    _announce("accumulate")
+    g = np.random.default_rng(12)
+    N, C, B, T, I = 32, 2, 20, 256, 16
+    pos = synth.line_positions(N)
+    dirs = synth.random_dirs(B, g)
+    freqs = np.array([402e6, 410e6])
+    x1 = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+    x2 = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+    import torch
+    with bf.Plan(N, C, B, T, I) as a, bf.Plan(N, C, B, T, I, accumulate=True) as b:
+        a.set_weights(pos, dirs, freqs)
+        b.set_weights(pos, dirs, freqs)
+        p1 = run_plan(a, x1, gpu)
+        p2 = run_plan(a, x2, gpu)
+        acc = torch.from_numpy(p1).to(gpu)
+        b.run(torch.from_numpy(x2).to(gpu), acc)
+        torch.cuda.synchronize()
+        assert np.array_equal(acc.cpu().numpy(), (p1 + p2).astype(np.float32))
+
+
+# --- error paths ---------------------------------------------------------------
+
+def test_error_paths(gpu):
+    import torch
+    with bf.Plan(4, 1, 2, 16, 1) as plan:
+        x = torch.zeros((1, 16, 4, 2), dtype=torch.int8, device=gpu)
+        p = torch.zeros((1, 2, 16), dtype=torch.float32, device=gpu)
+        with pytest.raises(bf.BfError) as e:
+            plan.run(x, p)
+        assert e.value.status == bf.ERR_STATE
+        with pytest.raises(bf.BfError) as e:
+            plan.set_weights(np.zeros((4, 3)), np.ones((2, 3)), [400e6])
+        assert e.value.status == bf.ERR_INVALID_ARG
+        with pytest.raises(bf.BfError) as e:
+            plan.set_weights(np.zeros((4, 3)), [[0, 0, 1], [0, 0, 1]], [-1.0])
+        assert e.value.status == bf.ERR_INVALID_ARG
+        plan.set_weights(np.zeros((4, 3)), [[0, 0, 1], [0, 0, 1]], [400e6])
+        buf = torch.zeros(1 * 16 * 4 * 2 + 1, dtype=torch.int8, device=gpu)
+        with pytest.raises(bf.BfError) as e:
+            plan.run_ptr(buf.data_ptr() + 1, p.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        assert e.value.status == bf.ERR_INVALID_ARG
+        with pytest.raises(bf.BfError) as e:
+            plan.set_tile(4, 3, 1, 1)
+        assert e.value.status == bf.ERR_UNSUPPORTED
+        plan.run(x, p)
+        torch.cuda.synchronize()
+        assert float(p.abs().sum()) == 0.0
