@@ -40,7 +40,22 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other-precision legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--retune", action="store_true", help="re-run the autotuner")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run device-to-device copies of BYTES (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(nbytes: int, reps: int = 3) -> None:
+    """A plain copy kernel of known size, for scaling rocprofv3 FETCH_SIZE /
+    WRITE_SIZE readings: each dispatch reads and writes nbytes."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(7)
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def workload(name):
@@ -123,12 +138,15 @@ def load_traffic(kernel_key: str):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(channel-sharded multi-GPU operation is a design note only)"}))
         sys.exit(2)
     import torch
-    from paper_1412_4907_amd import bf
+    from paper_1412_4907_amd import bf, tune
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -144,6 +162,9 @@ def main():
         plan = bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration, precision=prec)
         plan.set_weights(w.pos, w.dirs, w.freqs)
         p = torch.empty((w.n_chan, w.n_beams, windows), dtype=torch.float32, device=dev)
+        # tile shape from the autotuner's cache, else tuned now (untimed)
+        if a.retune or tune.apply_cached(plan) is None:
+            tune.tune(plan, xd, p, reps=3)
         per, total = time_plan(plan, xd, p, steps, warmup, torch)
         info = plan.info()
         plan.destroy()
@@ -176,8 +197,9 @@ def main():
                                f"B={w.n_beams} beams, T={w.n_samples} samples, I={w.integration}",
                    "precision": a.precision, "n_antennas": w.n_ant, "n_channels": w.n_chan,
                    "n_beams": w.n_beams, "n_samples": w.n_samples, "integration": w.integration,
-                   "tile": [info["tile_mt"], info["tile_nbt"], info["tile_nbp"],
-                            info["sg_per_wave"]],
+                   "tile": {"mt": info["tile_mt"], "nbt": info["tile_nbt"],
+                            "nbp": info["tile_nbp"], "kres": info["tile_kres"],
+                            "sg_per_wave": info["sg_per_wave"]},
                    "work_units": info["work_units"]},
         "mfma_peak_frac": round(value / peak, 4),
         "real_time_factor": round(block_s / (ms * 1e-3), 1),

@@ -149,6 +149,7 @@ typedef struct {
   int32_t tile_mt;        /* 16-sample MFMA row tiles per wave step             */
   int32_t tile_nbt;       /* 16-beam tiles per workgroup                        */
   int32_t tile_nbp;       /* 16-beam tiles per accumulator pass                 */
+  int32_t tile_kres;      /* 64-element K chunks held in registers (0: streamed) */
   int32_t sg_per_wave;    /* 16-window store groups per wave per work unit      */
   int64_t work_units;     /* workgroups of one bf_run                           */
   int64_t weight_bytes;   /* device bytes of the weight buffer                  */
@@ -158,12 +159,25 @@ typedef struct {
 int bf_plan_info(bf_plan_t plan, bf_plan_info_t* info);
 
 /*
- * Override the plan's tile choice (used by the autotuner).  mt in {4, 8},
- * nbt in {1, 2, 4, 8}, nbp in {1, 2, 4} with nbp <= nbt, sg_per_wave >= 1.
- * A combination this build does not instantiate returns BF_ERR_UNSUPPORTED
- * and leaves the plan unchanged.
+ * Override the plan's tile choice (used by the autotuner): mt row tiles of
+ * 16 samples per wave step, nbt 16-beam tiles per workgroup, nbp beam tiles
+ * per accumulator pass, kres K chunks of 64 held in registers (0 = streamed
+ * K), sg_per_wave 16-window store groups per wave per work unit.  A
+ * combination this build does not compile, or that the plan's K or LDS
+ * budget excludes, returns BF_ERR_UNSUPPORTED and leaves the plan unchanged;
+ * sg_per_wave * (row tiles per store group) must be a multiple of mt
+ * (else BF_ERR_INVALID_ARG).  The choice never changes the results.
  */
-int bf_plan_set_tile(bf_plan_t plan, int32_t mt, int32_t nbt, int32_t nbp, int32_t sg_per_wave);
+int bf_plan_set_tile(bf_plan_t plan, int32_t mt, int32_t nbt, int32_t nbp, int32_t kres,
+                     int32_t sg_per_wave);
+
+/*
+ * List the compiled tile variants that can run this plan: writes up to
+ * max_tiles rows of (mt, nbt, nbp, kres) into tiles[][4] and returns how
+ * many exist (which may exceed max_tiles; tiles may be NULL when
+ * max_tiles == 0), or BF_ERR_INVALID_ARG.
+ */
+int bf_plan_tile_candidates(bf_plan_t plan, int32_t* tiles, int32_t max_tiles);
 
 /* Free the plan.  Waits for the plan's outstanding device work first.
  * NULL is accepted (no-op). */

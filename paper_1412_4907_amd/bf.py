@@ -23,8 +23,9 @@ ACCUMULATE = 1
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 
 # every entry point declared in include/bf.h
-EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_plan_create", "bf_plan_create_ex", "bf_set_weights",
-           "bf_set_weights_raw", "bf_get_weights", "bf_run", "bf_plan_info", "bf_plan_set_tile",
+EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_plan_create",
+           "bf_plan_create_ex", "bf_set_weights", "bf_set_weights_raw", "bf_get_weights",
+           "bf_run", "bf_plan_info", "bf_plan_set_tile", "bf_plan_tile_candidates",
            "bf_plan_destroy", "bf_batch_create", "bf_batch_run", "bf_batch_destroy"]
 
 
@@ -43,7 +44,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_samples", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("k_padded", ctypes.c_int32), ("beams_padded", ctypes.c_int32),
                 ("tile_mt", ctypes.c_int32), ("tile_nbt", ctypes.c_int32),
-                ("tile_nbp", ctypes.c_int32), ("sg_per_wave", ctypes.c_int32),
+                ("tile_nbp", ctypes.c_int32), ("tile_kres", ctypes.c_int32),
+                ("sg_per_wave", ctypes.c_int32),
                 ("work_units", ctypes.c_int64), ("weight_bytes", ctypes.c_int64),
                 ("lds_bytes", ctypes.c_int64), ("flops", ctypes.c_double)]
 
@@ -74,7 +76,8 @@ def lib() -> ctypes.CDLL:
         L.bf_get_weights.argtypes = [P, P, P]
         L.bf_run.argtypes = [P, P, P, P]
         L.bf_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
-        L.bf_plan_set_tile.argtypes = [P, i32, i32, i32, i32]
+        L.bf_plan_set_tile.argtypes = [P, i32, i32, i32, i32, i32]
+        L.bf_plan_tile_candidates.argtypes = [P, P, i32]
         L.bf_plan_destroy.argtypes = [P]
         L.bf_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), i32]
         L.bf_batch_run.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
@@ -189,8 +192,22 @@ class Plan:
         _check(lib().bf_plan_info(self.handle, ctypes.byref(i)), "bf_plan_info")
         return i.as_dict()
 
-    def set_tile(self, mt: int, nbt: int, nbp: int, sg_per_wave: int) -> None:
-        _check(lib().bf_plan_set_tile(self.handle, mt, nbt, nbp, sg_per_wave), "bf_plan_set_tile")
+    def set_tile(self, mt: int, nbt: int, nbp: int, kres: int, sg_per_wave: int) -> None:
+        _check(lib().bf_plan_set_tile(self.handle, mt, nbt, nbp, kres, sg_per_wave),
+               "bf_plan_set_tile")
+
+    def tile_candidates(self) -> list:
+        """Compiled (mt, nbt, nbp, kres) variants that can run this plan."""
+        n = lib().bf_plan_tile_candidates(self.handle, None, 0)
+        if n < 0:
+            raise BfError(n, "bf_plan_tile_candidates")
+        arr = (ctypes.c_int32 * (4 * max(n, 1)))()
+        lib().bf_plan_tile_candidates(self.handle, ctypes.addressof(arr), n)
+        return [tuple(arr[4 * i:4 * i + 4]) for i in range(n)]
+
+    def tile(self) -> tuple:
+        i = self.info()
+        return (i["tile_mt"], i["tile_nbt"], i["tile_nbp"], i["tile_kres"], i["sg_per_wave"])
 
     def destroy(self) -> None:
         if getattr(self, "_h", None) is not None:

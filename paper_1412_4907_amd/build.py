@@ -20,6 +20,8 @@ SOURCES = ["bf_api.cpp", "bf_weights.hip", "bf_beamform_f32.hip", "bf_beamform_f
            "bf_beamform_bf16.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in VGPRs: the fused epilogue reads them with VALU
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", os.path.join(ROOT, "include")]
 
 

@@ -60,7 +60,9 @@ size_t lds_bytes(int prec, int Kpad, int nbt) {
   return (size_t)2 * 16 * nbt * ((size_t)Kpad * es_of(prec) + bf::kLdsPad);
 }
 
-int mode_of(int32_t I) { return I == 1 ? bf::kModeI1 : (I == 2 ? bf::kModeI2 : bf::kModeGen); }
+int mode_of(int32_t I) {
+  return I == 1 ? bf::kModeI1 : I == 2 ? bf::kModeI2 : (I % 4 == 0 ? bf::kModeGen4 : bf::kModeGen);
+}
 
 // Geometry of the row-tile schedule for integration I (see bf_beamform.inc).
 void schedule(int32_t I, int64_t T, int32_t* G, int32_t* QI, int32_t* SG) {
@@ -80,13 +82,25 @@ void schedule(int32_t I, int64_t T, int32_t* G, int32_t* QI, int32_t* SG) {
 
 int gcd(int a, int b) { return b ? gcd(b, a % b) : a; }
 
+const Tile kVecTiles[] = {
+#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
+    BF_TILE_LIST_VEC16
+#undef BF_TILE
+};
+const Tile kGenTiles[] = {
+#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
+    BF_TILE_LIST_GENERIC
+#undef BF_TILE
+};
+
 bool tile_exists(bool vec16, Tile t) {
-  static const Tile vec[] = {{4, 8, 2}, {8, 8, 2}, {4, 4, 4}, {8, 4, 2}, {4, 2, 2}, {4, 1, 1}};
-  static const Tile gen[] = {{4, 8, 2}, {4, 1, 1}};
-  const Tile* list = vec16 ? vec : gen;
-  int n = vec16 ? 6 : 2;
-  for (int i = 0; i < n; ++i)
-    if (list[i].mt == t.mt && list[i].nbt == t.nbt && list[i].nbp == t.nbp) return true;
+  if (vec16) {
+    for (const Tile& x : kVecTiles)
+      if (x.mt == t.mt && x.nbt == t.nbt && x.nbp == t.nbp && x.kres == t.kres) return true;
+  } else {
+    for (const Tile& x : kGenTiles)
+      if (x.mt == t.mt && x.nbt == t.nbt && x.nbp == t.nbp && x.kres == t.kres) return true;
+  }
   return false;
 }
 
@@ -99,24 +113,35 @@ int64_t units_for(const bf_plan_s* p, Tile t, int32_t sgw) {
   return (int64_t)p->C * nbr * ntr;
 }
 
-// Default tile: the largest beam tile whose weight slice fits 80 KB of LDS
-// (two workgroups per CU), MT = 8 on FP16/BF16 (more MFMA per fragment
-// load), then enough store groups per wave that a launch has >= 8
-// workgroups per CU without exceeding 256 row tiles per wave per unit.
+// Whether a compiled tile can run plan p.
+bool tile_ok(const bf_plan_s* p, Tile t) {
+  if (!tile_exists(p->vec16, t)) return false;
+  if (t.kres > 0 && p->Kpad / bf::kChunk > t.kres) return false;
+  return lds_bytes(p->prec, p->Kpad, t.nbt) <= kLdsMax;
+}
+
+// Default tile: the largest beam range whose weight slice fits 80 KB of LDS
+// (two workgroups per CU) without exceeding the plan's beams; voltages held
+// in registers when K <= 128 (MT = 8 for FP16/BF16 at K <= 64, where the
+// per-pass fragment reuse matters most); streamed K otherwise.  Then
+// enough store groups per wave that a launch has >= 8 workgroups per CU,
+// capped at 256 row tiles per wave per unit.
 void choose_tile(bf_plan_s* p) {
-  const int need = (p->Bpad / 16);
-  Tile t{4, 1, 1};
+  const int need = p->Bpad / 16;
+  const int nch = p->Kpad / bf::kChunk;
+  int nbt = 8;
+  while (nbt > 1 && (lds_bytes(p->prec, p->Kpad, nbt) > 80 * 1024 || nbt / 2 >= need)) nbt /= 2;
+  Tile t{4, 1, 1, 0};
   if (!p->vec16) {
-    t = (need >= 4 && lds_bytes(p->prec, p->Kpad, 8) <= 80 * 1024) ? Tile{4, 8, 2} : Tile{4, 1, 1};
+    t = nbt == 8 ? Tile{4, 8, 2, 0} : Tile{4, 1, 1, 0};
+  } else if (nch == 1 && nbt >= 4) {
+    t = (p->prec == BF_FP32) ? Tile{4, nbt, 1, 1} : Tile{8, nbt, 1, 1};
+  } else if (nch == 2 && nbt >= 4) {
+    t = Tile{4, nbt, 1, 2};
   } else {
-    int nbt = 8;
-    while (nbt > 1 && (lds_bytes(p->prec, p->Kpad, nbt) > 80 * 1024 || nbt / 2 >= need)) nbt /= 2;
-    if (p->prec == BF_FP32) {
-      t = nbt == 8 ? Tile{4, 8, 2} : nbt == 4 ? Tile{4, 4, 4} : nbt == 2 ? Tile{4, 2, 2} : Tile{4, 1, 1};
-    } else {
-      t = nbt == 8 ? Tile{8, 8, 2} : nbt == 4 ? Tile{8, 4, 2} : nbt == 2 ? Tile{4, 2, 2} : Tile{4, 1, 1};
-    }
+    t = nbt >= 4 ? Tile{4, nbt, 2, 0} : nbt == 2 ? Tile{4, 2, 2, 0} : Tile{4, 1, 1, 0};
   }
+  if (!tile_ok(p, t)) t = Tile{4, 1, 1, 0};
   int32_t G, QI, SG;
   schedule(p->I, p->T, &G, &QI, &SG);
   const int32_t base = t.mt / gcd(t.mt, G);  // sgw * G must be a multiple of MT
@@ -419,6 +444,7 @@ int bf_plan_info(bf_plan_t p, bf_plan_info_t* info) {
   info->tile_mt = p->tile.mt;
   info->tile_nbt = p->tile.nbt;
   info->tile_nbp = p->tile.nbp;
+  info->tile_kres = p->tile.kres;
   info->sg_per_wave = p->sgw;
   info->work_units = units_for(p, p->tile, p->sgw);
   info->weight_bytes = (int64_t)p->w_bytes;
@@ -427,17 +453,37 @@ int bf_plan_info(bf_plan_t p, bf_plan_info_t* info) {
   return BF_OK;
 }
 
-int bf_plan_set_tile(bf_plan_t p, int32_t mt, int32_t nbt, int32_t nbp, int32_t sgw) {
+int bf_plan_set_tile(bf_plan_t p, int32_t mt, int32_t nbt, int32_t nbp, int32_t kres,
+                     int32_t sgw) {
   if (!p || sgw < 1) return BF_ERR_INVALID_ARG;
-  Tile t{mt, nbt, nbp};
-  if (!tile_exists(p->vec16, t)) return BF_ERR_UNSUPPORTED;
-  if (lds_bytes(p->prec, p->Kpad, nbt) > kLdsMax) return BF_ERR_UNSUPPORTED;
+  Tile t{mt, nbt, nbp, kres};
+  if (!tile_ok(p, t)) return BF_ERR_UNSUPPORTED;
   int32_t G, QI, SG;
   schedule(p->I, p->T, &G, &QI, &SG);
   if (((int64_t)sgw * G) % mt != 0) return BF_ERR_INVALID_ARG;
   p->tile = t;
   p->sgw = sgw;
   return BF_OK;
+}
+
+int bf_plan_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
+  if (!p || max_tiles < 0 || (max_tiles > 0 && !tiles)) return BF_ERR_INVALID_ARG;
+  int32_t n = 0;
+  auto add = [&](const Tile& t) {
+    if (!tile_ok(p, t)) return;
+    if (n < max_tiles) {
+      tiles[4 * n + 0] = t.mt;
+      tiles[4 * n + 1] = t.nbt;
+      tiles[4 * n + 2] = t.nbp;
+      tiles[4 * n + 3] = t.kres;
+    }
+    ++n;
+  };
+  if (p->vec16)
+    for (const Tile& t : kVecTiles) add(t);
+  else
+    for (const Tile& t : kGenTiles) add(t);
+  return n;
 }
 
 int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n) {
@@ -474,16 +520,29 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
   try {
     if (!bt || !x || !out) return BF_ERR_INVALID_ARG;
     const int n = (int)bt->plans.size();
-    // One kernel instantiation serves the whole launch: the tile with the
-    // smallest beam range among the sets' own choices, which every set's
-    // LDS budget admits.  The numerics do not depend on the tile (same K
-    // order, same window sums), so each set's result equals its solo run.
-    Tile t = bt->plans[0]->tile;
+    // One kernel instantiation serves the whole launch: the first of the
+    // sets' own tiles (largest beam range first) that every set admits.
+    // The numerics do not depend on the tile (same K order, same window
+    // sums), so each set's result equals its solo run bit for bit.
     for (int i = 0; i < n; ++i) {
       const bf_plan_s* p = bt->plans[i];
       if (!x[i] || !out[i] || !aligned16(x[i]) || !aligned16(out[i])) return BF_ERR_INVALID_ARG;
       if (!p->weights_set) return BF_ERR_STATE;
-      if (p->tile.nbt < t.nbt || (p->tile.nbt == t.nbt && p->tile.mt < t.mt)) t = p->tile;
+    }
+    std::vector<Tile> cand;
+    for (int i = 0; i < n; ++i) cand.push_back(bt->plans[i]->tile);
+    std::stable_sort(cand.begin(), cand.end(), [](const Tile& a, const Tile& b) {
+      return a.nbt != b.nbt ? a.nbt > b.nbt : a.kres > b.kres;
+    });
+    cand.push_back(Tile{4, 1, 1, 0});
+    Tile t = cand.back();
+    for (const Tile& c : cand) {
+      bool ok = true;
+      for (int i = 0; i < n && ok; ++i) ok = tile_ok(bt->plans[i], c);
+      if (ok) {
+        t = c;
+        break;
+      }
     }
     Launch L;
     std::memset(&L, 0, sizeof(L));

@@ -13,8 +13,9 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kChunk = 64;      // real K elements (32 antennas) per chunk
 constexpr int kLdsPad = 16;     // bytes added to each LDS weight row
 
-// Integration classes; each is a separate kernel instantiation.
-enum Mode : int { kModeI1 = 0, kModeI2 = 1, kModeGen = 2 };
+// Integration classes; each is a separate kernel instantiation:
+// I == 1, I == 2, I >= 3 with I % 4 != 0 (padded windows), I % 4 == 0.
+enum Mode : int { kModeI1 = 0, kModeI2 = 1, kModeGen = 2, kModeGen4 = 3 };
 
 // One beam set (plan) inside a launch.  Lives in the kernel-argument
 // segment, so every field is read through scalar loads.
@@ -48,16 +49,25 @@ struct Launch {
 
 // Tile variant of the beamform kernel.
 struct Tile {
-  int mt;   // 16-row MFMA tiles per wave step
-  int nbt;  // 16-beam tiles per workgroup beam range
-  int nbp;  // 16-beam tiles per accumulator pass
+  int mt;    // 16-row MFMA tiles per wave step
+  int nbt;   // 16-beam tiles per workgroup beam range
+  int nbp;   // 16-beam tiles per accumulator pass
+  int kres;  // K chunks held in registers per wave step (0: streamed)
 };
+
+// Compiled tile variants: (MT, NBT, NBP, KRES).  KRES > 0 variants serve
+// plans with Kpad / 64 <= KRES.  The generic (byte-load) list serves
+// plans whose 2N is not a multiple of 16.
+#define BF_TILE_LIST_VEC16                                                        \
+  BF_TILE(8, 8, 1, 1) BF_TILE(4, 8, 2, 1) BF_TILE(4, 8, 1, 1) BF_TILE(8, 4, 1, 1)  \
+  BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 1, 2) BF_TILE(4, 8, 2, 0)  \
+  BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 2, 1, 0) BF_TILE(4, 1, 1, 0)
+#define BF_TILE_LIST_GENERIC BF_TILE(4, 8, 2, 0) BF_TILE(4, 1, 1, 0)
 
 // Host-side launcher for one (precision, mode, vec16, tile) instantiation.
 // Returns hipSuccess or the launch error.
 hipError_t launch_beamform(int prec, int mode, bool vec16, Tile tile, const Launch& L,
                            int grid, size_t lds_bytes, hipStream_t stream);
-bool tile_supported(int prec, Tile tile);
 
 hipError_t launch_weights_geom(int prec, const double* pos, const double* dir,
                                const double* freq, int N, int C, int B, int Bpad, int Kpad,

@@ -167,10 +167,12 @@ def test_deterministic_and_tile_invariant(gpu, prec):
         plan.set_weights(pos, dirs, freqs)
         base = run_plan(plan, x, gpu)
         assert np.array_equal(base, run_plan(plan, x, gpu))
-        for tile in [(4, 8, 2, 1), (8, 8, 2, 2), (4, 4, 4, 1), (8, 4, 2, 1), (4, 2, 2, 3),
-                     (4, 1, 1, 1)]:
-            plan.set_tile(*tile)
-            assert np.array_equal(base, run_plan(plan, x, gpu)), tile
+        cands = plan.tile_candidates()
+        assert len(cands) >= 8
+        for i, t in enumerate(cands):
+            sgw = [1, 2, 3, 4][i % 4] * (2 if t[0] == 8 else 1)
+            plan.set_tile(*t, sgw)
+            assert np.array_equal(base, run_plan(plan, x, gpu)), (t, sgw)
 
 
 # --- integration across blocks -------------------------------------------------
@@ -218,7 +220,7 @@ def test_error_paths(gpu):
             plan.run_ptr(buf.data_ptr() + 1, p.data_ptr(), torch.cuda.current_stream().cuda_stream)
         assert e.value.status == bf.ERR_INVALID_ARG
         with pytest.raises(bf.BfError) as e:
-            plan.set_tile(4, 3, 1, 1)
+            plan.set_tile(4, 3, 1, 0, 1)
         assert e.value.status == bf.ERR_UNSUPPORTED
         plan.run(x, p)
         torch.cuda.synchronize()
