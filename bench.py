@@ -36,11 +36,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"])
-    ap.add_argument("--workload", default="paper", choices=["paper", "small", "precision"])
+    ap.add_argument("--workload", default="paper",
+                    choices=["paper", "small", "precision", "serve", "batch"])
+    ap.add_argument("--blocks", type=int, default=40, help="serve: blocks to stream")
+    ap.add_argument("--pace", type=float, default=50.0,
+                    help="serve: replay speed-up over real time for the latency run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other-precision legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--retune", action="store_true", help="re-run the autotuner")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0,
+                    help="serve: HBM budget for admitted requests")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES (counter calibration)")
     return ap.parse_args()
@@ -136,6 +142,124 @@ def load_traffic(kernel_key: str):
     return e.get("bytes_per_launch")
 
 
+def serve_bench(a, torch, dev):
+    """Serving form: 256-antenna 16x16 array, blocks of 1024 channels x 8192
+    samples (524.288 ms each), FP16, I=64, seeded Poisson beam-set requests
+    (64..2048 beams, mean ~512 concurrently active) admitted by HBM footprint,
+    one batched launch per block replayed as a hipGraph.  Two runs: as fast as
+    the ring allows (throughput, real-time factor) and paced at ``--pace``x
+    real time (block latency p50/p99)."""
+    from paper_1412_4907_amd import serve, synth
+    prec = "fp16" if a.precision == "fp32" else a.precision
+    pos = synth.serve_array()
+    C, T, I = 1024, 8192, 64
+    freqs = synth.channel_freqs(C, 400e6, 16e6)
+    period = T / (16e6 / 1024)
+    t0 = time.perf_counter()
+    ring = []
+    for k in range(2):
+        blk = synth.serve_block(k)
+        ring.append(torch.from_numpy(blk.voltages(workers=16)).to(dev))
+    gen_s = time.perf_counter() - t0
+    reqs_spec = synth.serve_requests(64)
+    fp = lambda r: serve.footprint_bytes(r.n_beams, 256, C, T, I, prec)  # noqa: E731
+    budget = int(a.serve_budget_gb * (1 << 30))
+    out = {"metric": "beamforming TFLOP/s (8 flop/cMAC) + % MFMA peak; real-time factor, "
+                     "p99 block ms", "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
+           "config": {"workload": "serve: N=256 (16x16 grid, 10 m), C=1024, T=8192 per block "
+                                  "(524.288 ms), I=64, Poisson beam-set requests 64..2048 beams",
+                      "precision": prec, "hbm_budget_gb": a.serve_budget_gb,
+                      "ring_slots": len(ring)}}
+    for mode, pace in (("throughput", 0.0), ("paced", a.pace)):
+        reqs = [serve.Request(i, d, lifetime=life, arrival_block=arr)
+                for i, (arr, nb, life, d) in enumerate(reqs_spec)]
+        ex = serve.GpuExecutor(pos, freqs, T, I, prec, ring=ring)
+        sch = serve.Scheduler(budget, fp)
+        recs = serve.serve(ex, sch, reqs, n_blocks=a.blocks, block_period_s=period, pace=pace)
+        ex.close()
+        st = serve.summarize(recs, period)
+        beams = sum(r.beams for r in recs)
+        st["tflops"] = 8.0 * C * T * 256 * beams / st["wall_s"] / 1e12 if st["wall_s"] else None
+        st["graph_replays"] = ex.graph_replays
+        st["eager_launches"] = ex.eager_launches
+        st["requests_finished"] = len(sch.finished)
+        out[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+    thr = out["throughput"]
+    out["value"] = round(thr["tflops"], 3)
+    out["mfma_peak_frac"] = round(thr["tflops"] / PEAK_TFLOPS[prec], 4)
+    out["real_time_factor"] = thr["rtf"]
+    out["p50_block_ms"] = out["paced"]["p50_block_ms"]
+    out["p99_block_ms"] = out["paced"]["p99_block_ms"]
+    out["block_period_ms"] = round(period * 1e3, 3)
+    out["input_gen_s"] = round(gen_s, 1)
+    print(json.dumps(out), flush=True)
+
+
+def batch_bench(a, torch, dev):
+    """Batching form: the 12 seeded beam sets of uneven N, C, B, T in one
+    persistent launch (tiles from the autotuner cache or each set's default)."""
+    from paper_1412_4907_amd import bf, synth, tune
+    prec = a.precision
+    sets = synth.batch_sets()
+    plans, xs, ps = [], [], []
+    t0 = time.perf_counter()
+    flops = 0.0
+    abytes = 0.0
+    for w in sets:
+        plan = bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration, precision=prec)
+        plan.set_weights(w.pos, w.dirs, w.freqs)
+        plans.append(plan)
+        xs.append(torch.from_numpy(w.voltages(workers=16)).to(dev))
+        ps.append(torch.empty((w.n_chan, w.n_beams, w.n_samples // w.integration), device=dev))
+        # per-set tile from the autotuner, among the batching kernel's variants
+        if a.retune or tune.apply_cached(plan, batch=True) is None:
+            tune.tune(plan, xs[-1], ps[-1], reps=2, batch=True)
+        flops += w.flops
+        abytes += algorithmic_bytes(w, prec)
+    gen_s = time.perf_counter() - t0
+    batch = bf.Batch(plans)
+    stream = torch.cuda.current_stream()
+    for _ in range(a.warmup):
+        batch.run(xs, ps)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    ev[0].record(stream)
+    for i in range(a.steps):
+        batch.run(xs, ps)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(a.steps)]
+    ms = ev[0].elapsed_time(ev[a.steps]) / a.steps
+    # per-set solo time, for the batched-vs-sum comparison
+    solo_ms = 0.0
+    for plan, x, p in zip(plans, xs, ps):
+        s_per, s_total = time_plan(plan, x, p, 3, 1, torch)
+        solo_ms += s_total / 3
+    value = flops / (ms * 1e-3) / 1e12
+    # roofline fraction: sum over sets of max(flop/peak, bytes/bandwidth) / time
+    ideal = 0.0
+    for w in sets:
+        ideal += max(w.flops / (PEAK_TFLOPS[prec] * 1e12), algorithmic_bytes(w, prec) / (PEAK_HBM_GBS * 1e9))
+    out = {"metric": "beamforming TFLOP/s (8 flop/cMAC) + % MFMA peak; real-time factor, "
+                     "p99 block ms", "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": DTYPE[prec], "data": "synthetic",
+           "config": {"workload": "batch: 12 seeded beam sets, N in {16..256}, C in "
+                                  "{256,512,1024}, B in {16..1024}, T in [8192,32768], I=16",
+                      "sets": [[w.n_ant, w.n_chan, w.n_beams, w.n_samples] for w in sets]},
+           "roofline_frac": round(ideal * 1e3 / ms, 4),
+           "tiles": [list(p.tile()) for p in plans],
+           "sum_of_solo_ms": round(solo_ms, 4),
+           "p99_block_ms": round(float(np.percentile(per, 99)), 4),
+           "input_gen_s": round(gen_s, 1)}
+    batch.destroy()
+    for p in plans:
+        p.destroy()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -150,6 +274,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.workload == "serve":
+        return serve_bench(a, torch, dev)
+    if a.workload == "batch":
+        return batch_bench(a, torch, dev)
     w = workload(a.workload)
     t0 = time.perf_counter()
     x = w.voltages(workers=16)

@@ -196,6 +196,12 @@ int bf_plan_destroy(bf_plan_t plan);
  */
 int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n_plans);
 
+/* As bf_plan_tile_candidates, restricted to the variants the persistent
+ * batching kernel carries (a set whose own tile is among them runs with it
+ * inside a batch; otherwise the closest one is used).  Returns 0 for plans
+ * with 2N % 16 != 0, which batch under one common variant. */
+int bf_batch_tile_candidates(bf_plan_t plan, int32_t* tiles, int32_t max_tiles);
+
 /* x_dev[i], p_dev[i]: host arrays of device pointers, one per plan, same
  * layout and alignment rules as bf_run.  One launch on `stream` (after a
  * one-thread queue reset kernel).  Each set's output is bitwise identical to

@@ -26,7 +26,8 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = 0, -1, -2, -
 EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_plan_create",
            "bf_plan_create_ex", "bf_set_weights", "bf_set_weights_raw", "bf_get_weights",
            "bf_run", "bf_plan_info", "bf_plan_set_tile", "bf_plan_tile_candidates",
-           "bf_plan_destroy", "bf_batch_create", "bf_batch_run", "bf_batch_destroy"]
+           "bf_plan_destroy", "bf_batch_create", "bf_batch_tile_candidates", "bf_batch_run",
+           "bf_batch_destroy"]
 
 
 class BfError(RuntimeError):
@@ -78,6 +79,7 @@ def lib() -> ctypes.CDLL:
         L.bf_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
         L.bf_plan_set_tile.argtypes = [P, i32, i32, i32, i32, i32]
         L.bf_plan_tile_candidates.argtypes = [P, P, i32]
+        L.bf_batch_tile_candidates.argtypes = [P, P, i32]
         L.bf_plan_destroy.argtypes = [P]
         L.bf_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), i32]
         L.bf_batch_run.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
@@ -196,13 +198,15 @@ class Plan:
         _check(lib().bf_plan_set_tile(self.handle, mt, nbt, nbp, kres, sg_per_wave),
                "bf_plan_set_tile")
 
-    def tile_candidates(self) -> list:
-        """Compiled (mt, nbt, nbp, kres) variants that can run this plan."""
-        n = lib().bf_plan_tile_candidates(self.handle, None, 0)
+    def tile_candidates(self, batch: bool = False) -> list:
+        """Compiled (mt, nbt, nbp, kres) variants that can run this plan
+        (``batch``: those the persistent batching kernel carries)."""
+        fn = lib().bf_batch_tile_candidates if batch else lib().bf_plan_tile_candidates
+        n = fn(self.handle, None, 0)
         if n < 0:
-            raise BfError(n, "bf_plan_tile_candidates")
+            raise BfError(n, "tile candidates")
         arr = (ctypes.c_int32 * (4 * max(n, 1)))()
-        lib().bf_plan_tile_candidates(self.handle, ctypes.addressof(arr), n)
+        fn(self.handle, ctypes.addressof(arr), n)
         return [tuple(arr[4 * i:4 * i + 4]) for i in range(n)]
 
     def tile(self) -> tuple:

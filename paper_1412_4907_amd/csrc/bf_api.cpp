@@ -87,6 +87,11 @@ const Tile kVecTiles[] = {
     BF_TILE_LIST_VEC16
 #undef BF_TILE
 };
+const Tile kMultiTiles[] = {
+#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
+    BF_TILE_LIST_MULTI
+#undef BF_TILE
+};
 const Tile kGenTiles[] = {
 #define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
     BF_TILE_LIST_GENERIC
@@ -181,6 +186,7 @@ Prob make_prob(const bf_plan_s* p, const int8_t* x, float* out, int64_t unit_beg
   q.nbr = (p->Bpad / 16 + p->tile.nbt - 1) / p->tile.nbt;
   q.ntr = (int32_t)((SG + (int64_t)bf::kWaves * p->sgw - 1) / ((int64_t)bf::kWaves * p->sgw));
   q.accumulate = (p->flags & BF_ACCUMULATE) ? 1 : 0;
+  q.variant = -1;
   return q;
 }
 
@@ -486,6 +492,23 @@ int bf_plan_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
   return n;
 }
 
+int bf_batch_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
+  if (!p || max_tiles < 0 || (max_tiles > 0 && !tiles)) return BF_ERR_INVALID_ARG;
+  int32_t n = 0;
+  if (!p->vec16) return 0;
+  for (const Tile& t : kMultiTiles) {
+    if (!tile_ok(p, t)) continue;
+    if (n < max_tiles) {
+      tiles[4 * n + 0] = t.mt;
+      tiles[4 * n + 1] = t.nbt;
+      tiles[4 * n + 2] = t.nbp;
+      tiles[4 * n + 3] = t.kres;
+    }
+    ++n;
+  }
+  return n;
+}
+
 int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n) {
   try {
     if (!out) return BF_ERR_INVALID_ARG;
@@ -520,42 +543,64 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
   try {
     if (!bt || !x || !out) return BF_ERR_INVALID_ARG;
     const int n = (int)bt->plans.size();
-    // One kernel instantiation serves the whole launch: the first of the
-    // sets' own tiles (largest beam range first) that every set admits.
-    // The numerics do not depend on the tile (same K order, same window
-    // sums), so each set's result equals its solo run bit for bit.
     for (int i = 0; i < n; ++i) {
       const bf_plan_s* p = bt->plans[i];
       if (!x[i] || !out[i] || !aligned16(x[i]) || !aligned16(out[i])) return BF_ERR_INVALID_ARG;
       if (!p->weights_set) return BF_ERR_STATE;
     }
-    std::vector<Tile> cand;
-    for (int i = 0; i < n; ++i) cand.push_back(bt->plans[i]->tile);
-    std::stable_sort(cand.begin(), cand.end(), [](const Tile& a, const Tile& b) {
-      return a.nbt != b.nbt ? a.nbt > b.nbt : a.kres > b.kres;
-    });
-    cand.push_back(Tile{4, 1, 1, 0});
-    Tile t = cand.back();
-    for (const Tile& c : cand) {
-      bool ok = true;
-      for (int i = 0; i < n && ok; ++i) ok = tile_ok(bt->plans[i], c);
-      if (ok) {
-        t = c;
-        break;
-      }
-    }
     Launch L;
     std::memset(&L, 0, sizeof(L));
     int64_t begin = 0;
     size_t lds = 0;
+    const bool multi = bt->plans[0]->vec16;
+    Tile common{4, 1, 1, 0};
+    if (!multi) {
+      // byte-load (2N % 16 != 0) sets: one generic variant for all
+      std::vector<Tile> cand;
+      for (int i = 0; i < n; ++i) cand.push_back(bt->plans[i]->tile);
+      std::stable_sort(cand.begin(), cand.end(),
+                       [](const Tile& a, const Tile& b) { return a.nbt > b.nbt; });
+      for (const Tile& c : cand) {
+        bool ok = true;
+        for (int i = 0; i < n && ok; ++i) ok = tile_ok(bt->plans[i], c);
+        if (ok) {
+          common = c;
+          break;
+        }
+      }
+    }
     for (int i = 0; i < n; ++i) {
-      bf_plan_s tmp = *bt->plans[i];  // the same set under the launch-wide tile
+      bf_plan_s tmp = *bt->plans[i];  // the same set under its launch tile
+      Tile t = common;
+      int variant = -1;
+      if (multi) {
+        // the set's own tile if the batching kernel carries it, else the
+        // multi variant closest to it (same K residency, largest beam range)
+        const int nm = (int)(sizeof(kMultiTiles) / sizeof(kMultiTiles[0]));
+        for (int v = 0; v < nm && variant < 0; ++v) {
+          const Tile& c = kMultiTiles[v];
+          if (c.mt == tmp.tile.mt && c.nbt == tmp.tile.nbt && c.nbp == tmp.tile.nbp &&
+              c.kres == tmp.tile.kres && tile_ok(&tmp, c))
+            variant = v;
+        }
+        for (int v = 0; v < nm && variant < 0; ++v)
+          if (tile_ok(&tmp, kMultiTiles[v]) && kMultiTiles[v].kres == tmp.tile.kres &&
+              kMultiTiles[v].nbt <= tmp.tile.nbt)
+            variant = v;
+        for (int v = 0; v < nm && variant < 0; ++v)
+          if (tile_ok(&tmp, kMultiTiles[v])) variant = v;
+        if (variant < 0) return BF_ERR_UNSUPPORTED;
+        t = kMultiTiles[variant];
+      }
       int32_t G, QI, SG;
       schedule(tmp.I, tmp.T, &G, &QI, &SG);
       const int32_t base = t.mt / gcd(t.mt, G);
+      const bool same = t.mt == tmp.tile.mt && t.nbt == tmp.tile.nbt && t.nbp == tmp.tile.nbp &&
+                        t.kres == tmp.tile.kres;
       tmp.tile = t;
-      tmp.sgw = std::max(base, tmp.sgw / base * base);
+      tmp.sgw = same ? tmp.sgw : std::max(base, tmp.sgw / base * base);
       L.prob[i] = make_prob(&tmp, x[i], out[i], begin);
+      L.prob[i].variant = variant;
       begin += units_for(&tmp, t, tmp.sgw);
       lds = std::max(lds, lds_bytes(tmp.prec, tmp.Kpad, t.nbt));
     }
@@ -565,13 +610,22 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
     L.queue = bt->queue;
     L.xcd_remap = 0;
     const bf_plan_s* p0 = bt->plans[0];
-    const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+    int per_cu = lds <= 80 * 1024 ? 2 : 1;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (multi) {
+      int occ = 0;
+      e = bf::launch_beamform_multi(p0->prec, p0->mode, L, 0, lds, s, &occ);
+      if (e != hipSuccess) return from_hip(e);
+      per_cu = std::max(1, occ);
+    }
     int64_t grid = std::min<int64_t>(begin, (int64_t)p0->n_cu * per_cu);
     if (grid < 1) grid = 1;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = bf::launch_queue_reset(bt->queue, s);
-    if (e == hipSuccess)
-      e = bf::launch_beamform(p0->prec, p0->mode, p0->vec16, t, L, (int)grid, lds, s);
+    e = bf::launch_queue_reset(bt->queue, s);
+    if (e == hipSuccess) {
+      e = multi ? bf::launch_beamform_multi(p0->prec, p0->mode, L, (int)grid, lds, s, nullptr)
+                : bf::launch_beamform(p0->prec, p0->mode, p0->vec16, common, L, (int)grid, lds, s);
+    }
     return from_hip(e);
   } catch (...) {
     return BF_ERR_HIP;
@@ -596,6 +650,20 @@ hipError_t launch_prec(int mode, bool vec16, Tile t, const Launch& L, int grid, 
 extern template hipError_t launch_prec<0>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
 extern template hipError_t launch_prec<1>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
 extern template hipError_t launch_prec<2>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
+
+template <int PREC>
+hipError_t launch_multi_prec(int mode, const Launch& L, int grid, size_t lds, hipStream_t s,
+                             int* occupancy);
+extern template hipError_t launch_multi_prec<0>(int, const Launch&, int, size_t, hipStream_t, int*);
+extern template hipError_t launch_multi_prec<1>(int, const Launch&, int, size_t, hipStream_t, int*);
+extern template hipError_t launch_multi_prec<2>(int, const Launch&, int, size_t, hipStream_t, int*);
+
+hipError_t launch_beamform_multi(int prec, int mode, const Launch& L, int grid, size_t lds_bytes,
+                                 hipStream_t stream, int* occupancy) {
+  if (prec == 0) return launch_multi_prec<0>(mode, L, grid, lds_bytes, stream, occupancy);
+  if (prec == 1) return launch_multi_prec<1>(mode, L, grid, lds_bytes, stream, occupancy);
+  return launch_multi_prec<2>(mode, L, grid, lds_bytes, stream, occupancy);
+}
 
 hipError_t launch_beamform(int prec, int mode, bool vec16, Tile tile, const Launch& L, int grid,
                            size_t lds_bytes, hipStream_t stream) {

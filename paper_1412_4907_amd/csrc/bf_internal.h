@@ -36,7 +36,7 @@ struct Prob {
   int32_t QI;         // MFMA row tiles per window (general mode)
   int32_t SG;         // store groups per channel
   int32_t accumulate; // add into P instead of overwriting
-  int32_t pad_;
+  int32_t variant;    // multi-variant launches: index into BF_TILE_LIST_MULTI
 };
 
 struct Launch {
@@ -63,11 +63,21 @@ struct Tile {
   BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 1, 2) BF_TILE(4, 8, 2, 0)  \
   BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 2, 1, 0) BF_TILE(4, 1, 1, 0)
 #define BF_TILE_LIST_GENERIC BF_TILE(4, 8, 2, 0) BF_TILE(4, 1, 1, 0)
+// Variants compiled into the persistent batching kernel (16-byte loads).
+// (MT = 8 variants are left out: their register use would halve the
+// kernel's occupancy for every set.)
+#define BF_TILE_LIST_MULTI                                                        \
+  BF_TILE(4, 8, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0)  \
+  BF_TILE(4, 1, 1, 0)
 
 // Host-side launcher for one (precision, mode, vec16, tile) instantiation.
 // Returns hipSuccess or the launch error.
 hipError_t launch_beamform(int prec, int mode, bool vec16, Tile tile, const Launch& L,
                            int grid, size_t lds_bytes, hipStream_t stream);
+// Persistent batching kernel (per-set variants); occupancy != null only
+// queries workgroups per CU.
+hipError_t launch_beamform_multi(int prec, int mode, const Launch& L, int grid, size_t lds_bytes,
+                                 hipStream_t stream, int* occupancy);
 
 hipError_t launch_weights_geom(int prec, const double* pos, const double* dir,
                                const double* freq, int N, int C, int B, int Bpad, int Kpad,

@@ -1,0 +1,329 @@
+"""Streaming serve loop: continuous batching of beam-set requests over a
+stream of voltage blocks, one batched launch per block, captured as a
+hipGraph.
+
+Sec. 2.2 observes that a beamforming pipeline spends half its time waiting
+for voltages over PCIe and proposes overlapping copies with compute on a
+second stream; Sec. 3.2 recomputes weights while the previous iteration runs
+and keeps beams on the device for downstream stages.  The serving form here
+builds those ideas on one MI355X:
+
+* blocks (C channels x T samples x N antennas, int8) land in a ring of HBM
+  slots (pre-staged: the NIC-to-GPU assumption; or copied from pinned host
+  memory on a copy stream, the PCIe-bound variant);
+* beam-set requests (a set of pointings, a lifetime in blocks) arrive at any
+  time; at each block boundary the scheduler retires finished requests and
+  admits waiting ones while their HBM footprint (weights + double-buffered
+  output) fits the budget -- requests arriving while others run join the
+  next block's launch (continuous batching, not a queue of whole jobs);
+* each admitted request owns a plan (weights generated on the device once,
+  at admission) and two output buffers; integration state never leaves HBM;
+* the per-block work for the active set -- one queue-reset kernel and one
+  persistent beamform launch over every active request -- is captured once
+  per (active set, ring slot) as a hipGraph and replayed;
+* per block: arrival time, completion event, latency, and the real-time
+  factor (block period / processing time) are recorded.
+
+A request's output is bitwise the same whether it runs alone or in a mix
+(each work unit depends only on its own set's voltages and weights).
+
+The scheduler (``Scheduler``) is pure Python and is unit-tested on the CPU
+with a fake executor; ``GpuExecutor`` runs the C ABI.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    """A beam-set request: ``dirs`` [B][3] unit pointings, alive for
+    ``lifetime`` blocks from admission (None = until cancelled)."""
+    rid: int
+    dirs: np.ndarray
+    lifetime: Optional[int] = None
+    arrival_block: int = 0
+    # filled by the scheduler
+    admitted_block: Optional[int] = None
+    finished_block: Optional[int] = None
+    blocks_done: int = 0
+    failed: Optional[str] = None
+
+    @property
+    def n_beams(self) -> int:
+        return int(self.dirs.shape[0])
+
+
+def footprint_bytes(n_beams: int, n_ant: int, n_chan: int, n_samples: int, integration: int,
+                    precision: str, out_buffers: int = 2) -> int:
+    """Device bytes one admitted request holds: its weight buffer in the
+    MFMA operand layout plus ``out_buffers`` integrated-power outputs."""
+    es = 4 if precision == "fp32" else 2
+    bpad = -(-n_beams // 16) * 16
+    kpad = -(-2 * n_ant // 64) * 64
+    w = n_chan * bpad * 2 * kpad * es
+    p = n_chan * n_beams * (n_samples // integration) * 4
+    return int(w + out_buffers * p)
+
+
+@dataclass
+class BlockRecord:
+    block: int
+    active: List[int]
+    beams: int
+    arrival_s: float
+    done_s: float = 0.0
+
+    @property
+    def latency_ms(self) -> float:
+        return (self.done_s - self.arrival_s) * 1e3
+
+
+class Scheduler:
+    """Admission, retirement and footprint accounting (no device work)."""
+
+    def __init__(self, budget_bytes: int, fp: Callable[[Request], int], max_active: int = 16):
+        self.budget = int(budget_bytes)
+        self.fp = fp
+        self.max_active = max_active
+        self.waiting: List[Request] = []
+        self.active: Dict[int, Request] = {}
+        self.finished: List[Request] = []
+        self.rejected: List[Request] = []
+        self.used = 0
+
+    def submit(self, r: Request) -> None:
+        if self.fp(r) > self.budget:
+            r.failed = "footprint exceeds the whole budget"
+            self.rejected.append(r)
+            return
+        self.waiting.append(r)
+
+    def cancel(self, rid: int) -> None:
+        if rid in self.active:
+            self.active[rid].lifetime = self.active[rid].blocks_done
+        self.waiting = [r for r in self.waiting if r.rid != rid]
+
+    def fail(self, rid: int, why: str, block: int) -> None:
+        r = self.active.pop(rid, None)
+        if r is not None:
+            r.failed = why
+            r.finished_block = block
+            self.used -= self.fp(r)
+            self.finished.append(r)
+
+    def step(self, block: int):
+        """At a block boundary: retire finished requests, admit waiting ones
+        in arrival order while they fit.  Returns (admitted, retired)."""
+        retired = []
+        for rid in list(self.active):
+            r = self.active[rid]
+            if r.lifetime is not None and r.blocks_done >= r.lifetime:
+                r.finished_block = block
+                self.used -= self.fp(r)
+                retired.append(self.active.pop(rid))
+        self.finished.extend(retired)
+        admitted = []
+        still = []
+        for r in self.waiting:
+            if r.arrival_block > block:
+                still.append(r)
+                continue
+            f = self.fp(r)
+            if len(self.active) < self.max_active and self.used + f <= self.budget:
+                r.admitted_block = block
+                self.active[r.rid] = r
+                self.used += f
+                admitted.append(r)
+            else:
+                still.append(r)
+        self.waiting = still
+        return admitted, retired
+
+    def block_done(self, block: int) -> None:
+        for r in self.active.values():
+            r.blocks_done += 1
+
+
+class GpuExecutor:
+    """Runs the per-block batched launch through the C ABI, as a hipGraph
+    per (active set, ring slot)."""
+
+    def __init__(self, pos: np.ndarray, freqs: np.ndarray, n_samples: int, integration: int,
+                 precision: str = "fp16", ring: Sequence = (), use_graphs: bool = True):
+        import torch
+        from . import bf, tune
+        self.torch, self.bf, self.tune = torch, bf, tune
+        self.pos, self.freqs = pos, freqs
+        self.N, self.C = pos.shape[0], freqs.shape[0]
+        self.T, self.I = n_samples, integration
+        self.precision = precision
+        self.ring = list(ring)           # device int8 [C][T][N][2] tensors
+        self.use_graphs = use_graphs
+        self.stream = torch.cuda.Stream()
+        self.plans: Dict[int, object] = {}
+        self.outs: Dict[int, List] = {}
+        self.graphs: Dict[tuple, object] = {}
+        self.batches: Dict[tuple, object] = {}
+        self.graveyard: List = []
+        self.graveyard_outs: List = []
+        self.graveyard_held = 0
+        self.graveyard_bytes = 8 << 30
+        self.eager_launches = 0
+        self.graph_replays = 0
+
+    def admit(self, r: Request) -> None:
+        torch = self.torch
+        plan = self.bf.Plan(self.N, self.C, r.n_beams, self.T, self.I, precision=self.precision)
+        with torch.cuda.stream(self.stream):
+            plan.set_weights(self.pos, r.dirs, self.freqs, stream=self.stream)
+            self.outs[r.rid] = [torch.empty((self.C, r.n_beams, self.T // self.I),
+                                            dtype=torch.float32, device="cuda")
+                                for _ in range(2)]
+        self.tune.apply_cached(plan)
+        self.plans[r.rid] = plan
+
+    def retire(self, r: Request) -> None:
+        """Drop a request.  Freeing device memory synchronises the device,
+        so plans, batches and outputs go to a graveyard that is emptied
+        when it grows past ``graveyard_bytes`` or at close()."""
+        for k in [k for k in self.graphs if r.rid in k[0]]:
+            del self.graphs[k]
+        for k in [k for k in self.batches if r.rid in k]:
+            self.graveyard.append(self.batches.pop(k))
+        outs = self.outs.pop(r.rid, None)
+        p = self.plans.pop(r.rid, None)
+        if p is not None:
+            self.graveyard.append(p)
+            self.graveyard_held += sum(int(o.numel()) * 4 for o in (outs or []))
+            self.graveyard_outs.extend(outs or [])
+        if self.graveyard_held > self.graveyard_bytes:
+            self.flush_graveyard()
+
+    def flush_graveyard(self) -> None:
+        self.stream.synchronize()
+        for obj in self.graveyard:
+            obj.destroy()
+        self.graveyard.clear()
+        self.graveyard_outs.clear()
+        self.graveyard_held = 0
+
+    def _batch(self, ids: tuple):
+        b = self.batches.get(ids)
+        if b is None:
+            b = self.bf.Batch([self.plans[i] for i in ids])
+            self.batches[ids] = b
+        return b
+
+    def _launch(self, ids: tuple, slot: int, parity: int) -> None:
+        b = self._batch(ids)
+        xs = [self.ring[slot]] * len(ids)
+        ps = [self.outs[i][parity] for i in ids]
+        b.run(xs, ps, stream=self.stream)
+
+    def run_block(self, ids: Sequence[int], slot: int, parity: int):
+        """Enqueue one block's work on the serve stream; returns an event
+        recorded after it."""
+        torch = self.torch
+        ids = tuple(sorted(ids))
+        if ids:
+            key = (ids, slot, parity)
+            g = self.graphs.get(key) if self.use_graphs else None
+            if g is None:
+                # first use of this active set: run eagerly (also the warm-up
+                # that keeps one-time runtime calls out of the capture), then
+                # capture the same launch for later blocks
+                self._launch(ids, slot, parity)
+                self.eager_launches += 1
+                if self.use_graphs:
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=self.stream):
+                        self._launch(ids, slot, parity)
+                    self.graphs[key] = g
+            else:
+                with torch.cuda.stream(self.stream):
+                    g.replay()
+                self.graph_replays += 1
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        return ev
+
+    def output(self, rid: int, parity: int):
+        return self.outs[rid][parity]
+
+    def close(self) -> None:
+        self.stream.synchronize()
+        self.graphs.clear()
+        for k in list(self.batches):
+            self.batches.pop(k).destroy()
+        for p in self.plans.values():
+            p.destroy()
+        self.plans.clear()
+        self.outs.clear()
+        self.flush_graveyard()
+
+
+def serve(executor, scheduler: Scheduler, requests: Sequence[Request], n_blocks: int,
+          block_period_s: float, pace: float = 0.0, on_block=None) -> List[BlockRecord]:
+    """Run ``n_blocks`` blocks.  ``pace`` > 0 releases block k at
+    k * block_period_s / pace seconds after start (a replay ``pace`` times
+    faster than real time); 0 releases each block as soon as its ring slot is
+    free.  Returns one record per block (latency = release -> completion)."""
+    pending = sorted(requests, key=lambda r: r.arrival_block)
+    pi = 0
+    records: List[BlockRecord] = []
+    inflight = []  # (event, record)
+    n_slots = max(1, len(getattr(executor, "ring", [None])))
+    t0 = time.perf_counter()
+    for k in range(n_blocks):
+        while pi < len(pending) and pending[pi].arrival_block <= k:
+            scheduler.submit(pending[pi])
+            pi += 1
+        admitted, retired = scheduler.step(k)
+        for r in retired:
+            executor.retire(r)
+        for r in admitted:
+            try:
+                executor.admit(r)
+            except Exception as e:  # a request that cannot start fails alone
+                scheduler.fail(r.rid, f"admission failed: {e}", k)
+        # ring slot k % n_slots must be free: wait for block k - n_slots
+        while len(inflight) >= n_slots:
+            ev, rec = inflight.pop(0)
+            ev.synchronize()
+            rec.done_s = time.perf_counter() - t0
+        if pace > 0:
+            release = k * block_period_s / pace
+            now = time.perf_counter() - t0
+            if release > now:
+                time.sleep(release - now)
+        rec = BlockRecord(k, sorted(scheduler.active), sum(r.n_beams for r in scheduler.active.values()),
+                          time.perf_counter() - t0)
+        ev = executor.run_block(rec.active, k % n_slots, k & 1)
+        inflight.append((ev, rec))
+        records.append(rec)
+        scheduler.block_done(k)
+        if on_block is not None:
+            on_block(k, rec)
+    for ev, rec in inflight:
+        ev.synchronize()
+        rec.done_s = time.perf_counter() - t0
+    for r in list(scheduler.active.values()):
+        executor.retire(r)
+    return records
+
+
+def summarize(records: Sequence[BlockRecord], block_period_s: float) -> dict:
+    lat = np.array([r.latency_ms for r in records])
+    wall = records[-1].done_s - records[0].arrival_s if records else 0.0
+    return {"blocks": len(records),
+            "rtf": (len(records) * block_period_s / wall) if wall > 0 else None,
+            "p50_block_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_block_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+            "max_block_ms": float(lat.max()) if len(lat) else None,
+            "mean_active_beams": float(np.mean([r.beams for r in records])) if records else 0.0,
+            "wall_s": wall}

@@ -289,14 +289,20 @@ def serve_block(block: int, n_chan: int = 1024, n_samples: int = 8192) -> Worklo
                     pos, np.zeros((0, 3)), channel_freqs(n_chan, 400e6, 16e6))
 
 
-def serve_requests(n: int, mean_beams: float = 512.0):
-    """Seeded beam-set requests: (arrival_block, n_beams, lifetime_blocks, dirs)."""
+def serve_requests(n: int, mean_concurrent_beams: float = 512.0, mean_lifetime: float = 4.0):
+    """Seeded beam-set requests for the serving form: Poisson arrivals (in
+    block units), beams log-uniform over 64..2048, lifetimes geometric with
+    the given mean; the arrival rate makes the mean number of concurrently
+    active beams ``mean_concurrent_beams``.  Returns (arrival_block,
+    n_beams, lifetime_blocks, dirs) tuples."""
     g = rng("serve", "req")
+    mean_b = (2048 - 64) / np.log(2048 / 64)          # mean of log-uniform 64..2048
+    rate = mean_concurrent_beams / (mean_lifetime * mean_b)  # requests per block
     reqs = []
     blk = 0.0
     for i in range(n):
-        blk += g.exponential(1.0)
-        nb = int(2 ** g.uniform(6, 11))  # log-uniform 64..2048
-        life = int(g.geometric(0.25))
+        blk += g.exponential(1.0 / rate)
+        nb = int(2 ** g.uniform(6, 11))
+        life = int(g.geometric(1.0 / mean_lifetime))
         reqs.append((int(blk), nb, life, random_dirs(nb, rng("serve", "reqdirs", i))))
     return reqs

@@ -69,8 +69,8 @@ def sgw_options(plan, tile) -> list:
     return opts or [base]
 
 
-def apply_cached(plan) -> Optional[tuple]:
-    e = load_cache().get(shape_key(plan))
+def apply_cached(plan, batch: bool = False) -> Optional[tuple]:
+    e = load_cache().get(shape_key(plan) + ("/batch" if batch else ""))
     if not e:
         return None
     try:
@@ -81,15 +81,16 @@ def apply_cached(plan) -> Optional[tuple]:
 
 
 def tune(plan, x, p, reps: int = 3, max_candidates: Optional[int] = None, save: bool = True,
-         verbose: bool = False) -> dict:
+         verbose: bool = False, batch: bool = False) -> dict:
     """Time every (tile, sgw) candidate on device tensors x, p; apply and
-    return the fastest.  ``p`` is overwritten."""
+    return the fastest.  ``p`` is overwritten.  ``batch``: only the variants
+    the persistent batching kernel carries (cached under a separate key)."""
     import torch
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
     xp, pp = x.data_ptr(), p.data_ptr()
     results = []
-    cands = plan.tile_candidates()
+    cands = plan.tile_candidates(batch=batch) or plan.tile_candidates()
     if max_candidates:
         cands = cands[:max_candidates]
     for t in cands:
@@ -115,6 +116,6 @@ def tune(plan, x, p, reps: int = 3, max_candidates: Optional[int] = None, save: 
     out = {"tile": list(best), "ms": best_ms, "candidates": len(results)}
     if save:
         d = load_cache()
-        d[shape_key(plan)] = out
+        d[shape_key(plan) + ("/batch" if batch else "")] = out
         save_cache(d)
     return out

@@ -1,0 +1,68 @@
+"""Serving form on the GPU (scaled-down serve shapes: the 16x16 array, FP16,
+I=64): requests arriving and leaving while others run share each block's
+launch (replayed as hipGraphs); every request's output for every block is
+bitwise equal to that request run alone on the same block."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4907_amd import bf, serve, synth
+from tests.gpu_util import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def test_serve_alone_equals_mix(gpu):
+    import torch
+    print("serve mix", flush=True)
+    pos = synth.serve_array()
+    C, T, I = 16, 2048, 64
+    freqs = synth.channel_freqs(C, 400e6, 16e6)
+    blocks = [synth.Workload(f"b{k}", 2000 + k, 256, C, 0, T, I, pos, np.zeros((0, 3)),
+                             freqs).voltages() for k in range(2)]
+    ring = [torch.from_numpy(b).to(gpu) for b in blocks]
+    g = np.random.default_rng(5)
+    reqs = [serve.Request(i, synth.random_dirs(int(nb), g), lifetime=int(life), arrival_block=int(a))
+            for i, (nb, life, a) in enumerate([(64, 4, 0), (20, 2, 0), (100, 3, 1), (33, 5, 2),
+                                                (16, 1, 3), (48, 3, 3)])]
+    fp = lambda r: serve.footprint_bytes(r.n_beams, 256, C, T, I, "fp16")  # noqa: E731
+    budget = fp(reqs[0]) + fp(reqs[2]) + fp(reqs[1])  # forces some requests to wait
+    ex = serve.GpuExecutor(pos, freqs, T, I, "fp16", ring=ring)
+    sch = serve.Scheduler(budget, fp)
+    snaps = {}
+
+    def grab(k, rec):
+        with torch.cuda.stream(ex.stream):
+            for rid in rec.active:
+                snaps[(rid, k)] = ex.output(rid, k & 1).clone()
+
+    recs = serve.serve(ex, sch, reqs, n_blocks=10, block_period_s=0.524288, on_block=grab)
+    torch.cuda.synchronize()
+    assert ex.graph_replays > 0 and ex.eager_launches > 0
+    assert any(len(r.active) >= 2 for r in recs)
+    for rec in recs:
+        assert sum(fp(r) for r in reqs if r.rid in rec.active) <= budget
+    assert all(r.failed is None for r in sch.finished)
+    # every request ran its full lifetime
+    for r in reqs:
+        assert r.blocks_done == r.lifetime, (r.rid, r.blocks_done, r.lifetime)
+    # alone == in the mix, bitwise, for every (request, block)
+    solo = {}
+    for r in reqs:
+        plan = bf.Plan(256, C, r.n_beams, T, I, precision="fp16")
+        plan.set_weights(pos, r.dirs, freqs)
+        for slot in range(2):
+            p = torch.empty((C, r.n_beams, T // I), device=gpu)
+            plan.run(ring[slot], p)
+            torch.cuda.synchronize()
+            solo[(r.rid, slot)] = p.cpu().numpy()
+        plan.destroy()
+    for (rid, k), t in snaps.items():
+        assert np.array_equal(t.cpu().numpy(), solo[(rid, k % 2)]), (rid, k)
+    # and one request against the oracle on two channels
+    r = reqs[2]
+    ref = oracle.beamform(oracle.weights(pos, r.dirs, freqs[:2]), blocks[1][:2], I)
+    assert_parity(solo[(r.rid, 1)][:2], ref, 2e-3, "serve fp16 vs oracle")
+    ex.close()
+    st = serve.summarize(recs, 0.524288)
+    print(st, flush=True)

@@ -1,0 +1,119 @@
+"""Serving-form scheduler on the CPU with a fake executor: admission by HBM
+footprint, retirement, cancellation, a failing request that does not stop
+the others, deadline accounting, and per-request results computed by the
+oracle on tiny shapes (alone == in the mix)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4907_amd import serve, synth
+
+
+class FakeEvent:
+    def synchronize(self):
+        pass
+
+
+class FakeExecutor:
+    """Oracle-backed executor on tiny shapes: block k's voltages are
+    regenerated from the seed; each active request's output is the oracle's
+    power for its own pointings."""
+
+    def __init__(self, pos, freqs, T, I, fail_ids=()):
+        self.pos, self.freqs, self.T, self.I = pos, freqs, T, I
+        self.ring = [None, None]
+        self.W = {}
+        self.out = {}
+        self.fail_ids = set(fail_ids)
+        self.launches = []
+
+    def admit(self, r):
+        if r.rid in self.fail_ids:
+            raise RuntimeError("simulated device allocation failure")
+        self.W[r.rid] = oracle.weights(self.pos, r.dirs, self.freqs)
+        self.out[r.rid] = {}
+
+    def retire(self, r):
+        self.W.pop(r.rid, None)
+
+    def run_block(self, ids, slot, parity):
+        self.launches.append(tuple(ids))
+        w = synth.Workload("t", 77, self.pos.shape[0], len(self.freqs), 0, self.T, self.I,
+                           self.pos, np.zeros((0, 3)), self.freqs)
+        x = np.stack([synth.channel_voltages(500 + len(self.launches), c, self.T, self.pos,
+                                             self.freqs[c]) for c in range(len(self.freqs))])
+        for i in ids:
+            self.out[i][len(self.launches) - 1] = oracle.beamform(self.W[i], x, self.I)
+        return FakeEvent()
+
+
+def _reqs(n, g, nb=(3, 5, 8)):
+    out = []
+    for i in range(n):
+        out.append(serve.Request(i, synth.random_dirs(int(g.choice(nb)), g),
+                                 lifetime=int(g.integers(1, 4)), arrival_block=int(g.integers(0, 6))))
+    return out
+
+
+def test_footprint_accounting_and_admission():
+    fp = lambda r: 100 * r.n_beams  # noqa: E731
+    s = serve.Scheduler(budget_bytes=1000, fp=fp)
+    a = serve.Request(0, np.zeros((6, 3)), lifetime=2)
+    b = serve.Request(1, np.zeros((5, 3)), lifetime=1)
+    c = serve.Request(2, np.zeros((4, 3)), lifetime=1)
+    huge = serve.Request(3, np.zeros((11, 3)), lifetime=1)
+    for r in (a, b, c, huge):
+        s.submit(r)
+    assert huge in s.rejected
+    adm, ret = s.step(0)
+    assert [r.rid for r in adm] == [0, 2] and s.used == 1000  # b (500) does not fit after a (600)
+    s.block_done(0)
+    adm, ret = s.step(1)        # c done (lifetime 1) -> b still does not fit next to a
+    assert [r.rid for r in ret] == [2] and [r.rid for r in adm] == []
+    s.block_done(1)
+    adm, ret = s.step(2)        # a done -> b admitted
+    assert sorted(r.rid for r in ret) == [0] and [r.rid for r in adm] == [1]
+    assert s.used == 500
+    s.cancel(1)
+    adm, ret = s.step(3)
+    assert [r.rid for r in ret] == [1] and s.used == 0
+
+
+def test_serve_loop_alone_equals_mix_with_failure():
+    g = np.random.default_rng(3)
+    pos = synth.disc_positions(5, 50.0, g)
+    freqs = np.array([401e6, 409e6])
+    T, I = 16, 4
+    reqs = _reqs(7, g)
+    fp = lambda r: serve.footprint_bytes(r.n_beams, 5, 2, T, I, "fp32")  # noqa: E731
+    budget = 3 * fp(serve.Request(0, np.zeros((8, 3))))
+    ex = FakeExecutor(pos, freqs, T, I, fail_ids={4})
+    sch = serve.Scheduler(budget, fp)
+    recs = serve.serve(ex, sch, reqs, n_blocks=12, block_period_s=0.0)
+    assert len(recs) == 12
+    st = serve.summarize(recs, 0.5)
+    assert st["blocks"] == 12
+    # request 4 failed alone; the others ran their full lifetime
+    r4 = [r for r in sch.finished if r.rid == 4][0]
+    assert r4.failed and "admission" in r4.failed
+    for r in sch.finished:
+        if r.rid != 4:
+            assert r.failed is None and r.blocks_done == r.lifetime
+    # footprint never exceeded the budget at any block
+    for rec in recs:
+        assert sum(fp(r) for r in reqs if r.rid in rec.active) <= budget
+    # each request's per-block output equals the request run alone on that block
+    for r in reqs:
+        if r.rid == 4:
+            continue
+        W = oracle.weights(pos, r.dirs, freqs)
+        for k, got in ex.out[r.rid].items():
+            w = synth.Workload("t", 77, 5, 2, 0, T, I, pos, np.zeros((0, 3)), freqs)
+            x = np.stack([synth.channel_voltages(500 + k + 1, c, T, pos, freqs[c]) for c in range(2)])
+            assert np.array_equal(got, oracle.beamform(W, x, I))
+
+
+def test_footprint_formula():
+    # FP16, N=256, C=1024, 2048 beams, T=8192, I=64: 4 GiB of weights + 2 x 1 GiB outputs
+    f = serve.footprint_bytes(2048, 256, 1024, 8192, 64, "fp16")
+    assert f == 1024 * 2048 * 2 * 512 * 2 + 2 * 1024 * 2048 * 128 * 4
