@@ -125,6 +125,37 @@ def cpu_baseline(w, budget_s: float) -> dict:
                       f"{dt:.1f} s FP64 on the host"}
 
 
+def precision_report(torch, dev, n_chan_check: int = 5) -> dict:
+    """Power error of each precision form against the FP64 oracle on the
+    512-beam precision workload (small array and voltages, I=1): per-beam
+    normwise error max/median over a seeded channel sample, plus the
+    accumulation-only error (oracle run on the GPU's own rounded weights)."""
+    import oracle
+    from paper_1412_4907_amd import bf, synth
+    w = synth.precision()
+    x = w.voltages()
+    chans = sorted(synth.rng("precision", "check").choice(w.n_chan, n_chan_check, replace=False))
+    ref = oracle.beamform(oracle.weights(w.pos, w.dirs, w.freqs[chans]), x[chans], 1)
+    xd = torch.from_numpy(x).to(dev)
+    rep = {"workload": "precision: N=32 line, C=128, B=512, T=4096, I=1",
+           "channels_checked": [int(c) for c in chans]}
+    for prec in ("fp32", "fp16", "bf16"):
+        plan = bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, 1, precision=prec)
+        plan.set_weights(w.pos, w.dirs, w.freqs)
+        p = torch.empty((w.n_chan, w.n_beams, w.n_samples), device=dev)
+        plan.run(xd, p)
+        torch.cuda.synchronize()
+        got = p[chans].cpu().numpy().astype(np.float64)
+        wq = plan.get_weights()[chans]
+        plan.destroy()
+        refq = oracle.beamform(wq, x[chans], 1)
+        e = np.linalg.norm(got - ref, axis=-1) / np.linalg.norm(ref, axis=-1)
+        eq = np.linalg.norm(got - refq, axis=-1) / np.linalg.norm(refq, axis=-1)
+        rep[prec] = {"power_err_max": float(e.max()), "power_err_median": float(np.median(e)),
+                     "accumulation_err_max": float(eq.max())}
+    return rep
+
+
 def load_traffic(kernel_key: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel build (else null)."""
@@ -357,6 +388,8 @@ def main():
                            "p99_block_ms": round(float(np.percentile(per2, 99)), 4)}
         out["other_precisions"] = extra
     del xd
+    if not a.no_extra:
+        out["precision_forms"] = precision_report(torch, dev)
     if not a.no_cpu_baseline:
         cb = cpu_baseline(w, a.cpu_seconds)
         out["cpu_baseline"] = cb

@@ -251,7 +251,7 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
       delete p;
       return BF_ERR_HIP;
     }
-    hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+    (void)hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
     if (p->n_cu < 1) p->n_cu = 256;
     if (lds_bytes(p->prec, p->Kpad, 1) > kLdsMax) {
       delete p;
@@ -264,9 +264,10 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
       delete p;
       return from_hip(e);
     }
-    e = hipMemset(p->w_dev, 0, p->w_bytes);
+    // no clearing: both weight kernels write every element of the buffer
+    // (padding included), and nothing reads it before one of them has run
     p->geo_count = (size_t)3 * N + (size_t)3 * B + (size_t)C;
-    if (e == hipSuccess) e = hipHostMalloc((void**)&p->geo_host, p->geo_count * sizeof(double), 0);
+    e = hipHostMalloc((void**)&p->geo_host, p->geo_count * sizeof(double), 0);
     if (e == hipSuccess) e = hipMalloc(&p->geo_dev, p->geo_count * sizeof(double));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->geo_done, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -288,14 +289,14 @@ int bf_plan_destroy(bf_plan_t p) {
   if (!p) return BF_OK;
   try {
     int dev = 0;
-    hipGetDevice(&dev);
-    hipSetDevice(p->device);
-    hipDeviceSynchronize();
-    if (p->w_dev) hipFree(p->w_dev);
-    if (p->geo_dev) hipFree(p->geo_dev);
-    if (p->geo_host) hipHostFree(p->geo_host);
-    if (p->geo_done) hipEventDestroy(p->geo_done);
-    hipSetDevice(dev);
+    (void)hipGetDevice(&dev);
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->w_dev) (void)hipFree(p->w_dev);
+    if (p->geo_dev) (void)hipFree(p->geo_dev);
+    if (p->geo_host) (void)hipHostFree(p->geo_host);
+    if (p->geo_done) (void)hipEventDestroy(p->geo_done);
+    (void)hipSetDevice(dev);
     delete p;
     return BF_OK;
   } catch (...) {
@@ -360,7 +361,7 @@ int bf_set_weights_raw(bf_plan_t p, const double* w, void* stream) {
     if (e == hipSuccess)
       e = bf::launch_weights_raw(p->prec, dw, p->N, p->C, p->B, p->Bpad, p->Kpad, p->w_dev, s);
     hipError_t e2 = hipStreamSynchronize(s);
-    hipFree(dw);
+    (void)hipFree(dw);
     if (e != hipSuccess) return from_hip(e);
     if (e2 != hipSuccess) return from_hip(e2);
     p->weights_set = true;
@@ -634,8 +635,8 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
 
 int bf_batch_destroy(bf_batch_t bt) {
   if (!bt) return BF_OK;
-  hipDeviceSynchronize();
-  if (bt->queue) hipFree(bt->queue);
+  (void)hipDeviceSynchronize();
+  if (bt->queue) (void)hipFree(bt->queue);
   delete bt;
   return BF_OK;
 }
