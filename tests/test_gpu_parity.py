@@ -135,6 +135,43 @@ def test_ragged_shapes(gpu, shape, prec):
     assert_parity(got, ref, TOL[prec], f"{shape} {prec}")
 
 
+# --- register-resident pipelined form (FP16/BF16) -------------------------------
+# Shapes the pipelined unit form serves (2N a multiple of 16, every K chunk in
+# registers, I == 1 or a multiple of the row-tile count, T/I a multiple of 4),
+# with beam counts that leave a partial last beam range, so pipelined and
+# general units share one launch.  Checked against the oracle, and bit for bit
+# against a streaming tile, which never takes the pipelined form (both sum each
+# window's samples in time order).  N = 24 leaves the last K slice past 2N,
+# which the pipelined form reads as zeros.
+
+FAST = [  # N, C, B, T, I
+    (8, 2, 130, 512, 4), (16, 2, 128, 1024, 8), (32, 3, 144, 960, 12), (32, 2, 256, 1280, 20),
+    (64, 2, 136, 2048, 64), (32, 2, 128, 1024, 1), (24, 1, 200, 768, 1),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("shape", FAST, ids=[f"N{s[0]}C{s[1]}B{s[2]}T{s[3]}I{s[4]}" for s in FAST])
+def test_pipelined_form(gpu, shape, prec):
+    N, C, B, T, I = shape
+    _announce(f"pipelined form {shape} {prec}")
+    g = np.random.default_rng(sum(shape) * 7 + len(prec))
+    pos = synth.disc_positions(N, 150.0, g)
+    dirs = synth.random_dirs(B, g)
+    freqs = np.linspace(401e6, 415e6, C)
+    x = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+    resident = (4, 8, 1, 1 if 2 * N <= 64 else 2, 4)
+    with bf.Plan(N, C, B, T, I, precision=prec) as plan:
+        plan.set_weights(pos, dirs, freqs)
+        plan.set_tile(*resident)
+        got = run_plan(plan, x, gpu)
+        plan.set_tile(4, 8, 2, 0, 4)
+        streamed = run_plan(plan, x, gpu)
+    ref = oracle.beamform(oracle.weights(pos, dirs, freqs), x, I)
+    assert_parity(got, ref, TOL[prec], f"{shape} {prec}")
+    assert np.array_equal(got, streamed), shape
+
+
 # --- integer-exact weights: bit-exact in every precision ------------------------
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
