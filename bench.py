@@ -38,9 +38,10 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "small", "precision", "serve", "batch"])
-    ap.add_argument("--blocks", type=int, default=40, help="serve: blocks to stream")
-    ap.add_argument("--pace", type=float, default=50.0,
-                    help="serve: replay speed-up over real time for the latency run")
+    ap.add_argument("--blocks", type=int, default=200, help="serve: blocks to stream")
+    ap.add_argument("--pace", type=float, default=10.0,
+                    help="serve: replay speed-up over real time for the latency run "
+                         "(Poisson block arrivals with mean gap block_period / pace)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other-precision legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -178,8 +179,9 @@ def serve_bench(a, torch, dev):
     samples (524.288 ms each), FP16, I=64, seeded Poisson beam-set requests
     (64..2048 beams, mean ~512 concurrently active) admitted by HBM footprint,
     one batched launch per block replayed as a hipGraph.  Two runs: as fast as
-    the ring allows (throughput, real-time factor) and paced at ``--pace``x
-    real time (block latency p50/p99)."""
+    the ring allows (throughput, real-time factor) and with seeded Poisson
+    block arrivals at ``--pace``x real time (block latency p50/p99, arrival to
+    completion)."""
     from paper_1412_4907_amd import serve, synth
     prec = "fp16" if a.precision == "fp32" else a.precision
     pos = synth.serve_array()
@@ -201,13 +203,17 @@ def serve_bench(a, torch, dev):
            "config": {"workload": "serve: N=256 (16x16 grid, 10 m), C=1024, T=8192 per block "
                                   "(524.288 ms), I=64, Poisson beam-set requests 64..2048 beams",
                       "precision": prec, "hbm_budget_gb": a.serve_budget_gb,
-                      "ring_slots": len(ring)}}
-    for mode, pace in (("throughput", 0.0), ("paced", a.pace)):
-        reqs = [serve.Request(i, d, lifetime=life, arrival_block=arr)
-                for i, (arr, nb, life, d) in enumerate(reqs_spec)]
+                      "ring_slots": len(ring), "blocks": a.blocks,
+                      "paced_arrivals": f"seeded Poisson, mean gap {period / a.pace * 1e3:.3f} ms "
+                                        f"({a.pace:g}x real time)"}}
+    arrivals = synth.serve_block_arrivals(a.blocks, period, a.pace)
+    for mode, arr in (("throughput", None), ("paced", arrivals)):
+        reqs = [serve.Request(i, d, lifetime=life, arrival_block=arr_b)
+                for i, (arr_b, nb, life, d) in enumerate(reqs_spec)]
         ex = serve.GpuExecutor(pos, freqs, T, I, prec, ring=ring)
         sch = serve.Scheduler(budget, fp)
-        recs = serve.serve(ex, sch, reqs, n_blocks=a.blocks, block_period_s=period, pace=pace)
+        recs = serve.serve(ex, sch, reqs, n_blocks=a.blocks, block_period_s=period,
+                           arrivals=arr)
         ex.close()
         st = serve.summarize(recs, period)
         beams = sum(r.beams for r in recs)

@@ -56,6 +56,7 @@ extern "C" {
 
 typedef struct bf_plan_s* bf_plan_t;
 typedef struct bf_batch_s* bf_batch_t;
+typedef struct bf_table_s* bf_table_t;
 
 typedef enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2 } bf_precision_t;
 
@@ -209,6 +210,47 @@ int bf_batch_tile_candidates(bf_plan_t plan, int32_t* tiles, int32_t max_tiles);
 int bf_batch_run(bf_batch_t batch, const int8_t* const* x_dev, float* const* p_dev, void* stream);
 
 int bf_batch_destroy(bf_batch_t batch);
+
+/*
+ * Table batch, for streaming use (a sequence of blocks whose set of active
+ * plans changes between blocks; Sec. 2.2 and Sec. 3.2 describe beamforming
+ * block after block while new pointings are prepared).  The same persistent
+ * kernel as bf_batch_run, but its set table lives in device memory owned by
+ * the table, so every bf_table_run enqueues the same two launches with the
+ * same arguments: a hipGraph captured around one bf_table_run serves every
+ * table stored afterwards.
+ *
+ * bf_table_create: for plans with n_antennas antennas, integration I and the
+ * given precision (2 n_antennas must be a multiple of 16) on the current
+ * device.  It fixes the launch: dynamic LDS of the largest batching variant
+ * that keeps two workgroups per CU, grid = CUs x workgroups per CU.  Owns a
+ * device table (a few KB) and a queue counter.
+ * Errors: BF_ERR_INVALID_ARG, BF_ERR_UNSUPPORTED, BF_ERR_OOM, BF_ERR_HIP.
+ */
+int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, int32_t precision);
+
+/* Stores the set table for the next bf_table_run on `stream`: plans[i] with
+ * voltages x_dev[i] and output p_dev[i] (device pointers, layout and
+ * alignment as bf_run), 0 <= n <= 16; n = 0 makes the next run a no-op.
+ * Every plan must match the table's antennas, integration, precision and
+ * device and have its weights set; each set runs its own tile if the
+ * batching kernel carries it and its LDS fits, else the closest that does.
+ * The store is a one-workgroup kernel on `stream` (the table travels as its
+ * argument), so the host arrays may be reused as soon as this returns; it is
+ * ordered with bf_table_run only through `stream`.  Plans and buffers must
+ * stay valid until the runs that use them have completed.  Each set's
+ * output is bitwise identical to bf_run of that plan alone.
+ * Errors: BF_ERR_INVALID_ARG, BF_ERR_UNSUPPORTED, BF_ERR_STATE, BF_ERR_HIP. */
+int bf_table_set(bf_table_t table, const bf_plan_t* plans, const int8_t* const* x_dev,
+                 float* const* p_dev, int32_t n, void* stream);
+
+/* Enqueues the batched launch over the stored table on `stream` (queue reset
+ * kernel + persistent kernel; no allocation, no memset, no host sync), so it
+ * may be captured into a hipGraph.  Runs on one stream must not overlap: they
+ * share the table and the queue counter. */
+int bf_table_run(bf_table_t table, void* stream);
+
+int bf_table_destroy(bf_table_t table);
 
 #ifdef __cplusplus
 }

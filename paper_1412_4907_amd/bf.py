@@ -27,7 +27,8 @@ EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_plan_create",
            "bf_plan_create_ex", "bf_set_weights", "bf_set_weights_raw", "bf_get_weights",
            "bf_run", "bf_plan_info", "bf_plan_set_tile", "bf_plan_tile_candidates",
            "bf_plan_destroy", "bf_batch_create", "bf_batch_tile_candidates", "bf_batch_run",
-           "bf_batch_destroy"]
+           "bf_batch_destroy", "bf_table_create", "bf_table_set", "bf_table_run",
+           "bf_table_destroy"]
 
 
 class BfError(RuntimeError):
@@ -84,6 +85,10 @@ def lib() -> ctypes.CDLL:
         L.bf_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), i32]
         L.bf_batch_run.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
         L.bf_batch_destroy.argtypes = [P]
+        L.bf_table_create.argtypes = [ctypes.POINTER(P), i32, i32, i32]
+        L.bf_table_set.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), i32, P]
+        L.bf_table_run.argtypes = [P, P]
+        L.bf_table_destroy.argtypes = [P]
         for name in EXPORTS[3:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -253,6 +258,45 @@ class Batch:
     def destroy(self) -> None:
         if getattr(self, "_h", None) is not None:
             lib().bf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Table:
+    """Persistent batched launch over a set table kept in device memory
+    (``bf_table_create``): ``set`` stores which plans run on which buffers,
+    ``run`` enqueues the same two launches every time, so a graph captured
+    around one ``run`` serves every later ``set``."""
+
+    def __init__(self, n_antennas: int, integration: int, precision="fp16"):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        _check(lib().bf_table_create(ctypes.byref(h), int(n_antennas), int(integration), prec),
+               "bf_table_create")
+        self._h = h
+
+    def set(self, plans: Sequence[Plan], xs, ps, stream=None) -> None:
+        if len(xs) != len(plans) or len(ps) != len(plans):
+            raise ValueError("one x and one p per plan")
+        for pl, x, p in zip(plans, xs, ps):
+            pl.check_io(x, p)
+        n = len(plans)
+        ha = (ctypes.c_void_p * max(n, 1))(*[pl.handle.value for pl in plans])
+        xa = (ctypes.c_void_p * max(n, 1))(*[x.data_ptr() for x in xs])
+        pa = (ctypes.c_void_p * max(n, 1))(*[p.data_ptr() for p in ps])
+        _check(lib().bf_table_set(self._h, ha, xa, pa, n, _stream_ptr(stream)), "bf_table_set")
+
+    def run(self, stream=None) -> None:
+        _check(lib().bf_table_run(self._h, _stream_ptr(stream)), "bf_table_run")
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().bf_table_destroy(self._h)
             self._h = None
 
     def __del__(self):

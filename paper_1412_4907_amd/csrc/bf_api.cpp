@@ -47,6 +47,18 @@ struct bf_batch_s {
   int device = 0;
 };
 
+struct bf_table_s {
+  int32_t N = 0, I = 0;
+  int prec = 0, mode = 0;
+  int32_t Kpad = 0;
+  size_t lds = 0;     // fixed dynamic LDS of every launch
+  int grid = 1;       // fixed persistent grid: CUs x workgroups per CU
+  int device = 0;
+  int n_cu = 256;
+  int32_t* queue = nullptr;
+  Launch* table = nullptr;  // device copy of the set table
+};
+
 namespace {
 
 constexpr int kMaxN = 4096;
@@ -202,6 +214,80 @@ int from_hip(hipError_t e) {
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// The set table of a batched launch: each set's tile (its own if the
+// persistent kernel carries it, else the closest carried variant whose LDS
+// fits lds_cap), unit ranges and the largest LDS size any set needs.
+// Byte-load sets (2N % 16 != 0) share one generic variant (*common).
+int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* const* out,
+              size_t lds_cap, Launch* L, size_t* lds_out, Tile* common) {
+  std::memset(L, 0, sizeof(*L));
+  for (int i = 0; i < n; ++i) {
+    const bf_plan_s* p = plans[i];
+    if (!x[i] || !out[i] || !aligned16(x[i]) || !aligned16(out[i])) return BF_ERR_INVALID_ARG;
+    if (!p->weights_set) return BF_ERR_STATE;
+  }
+  int64_t begin = 0;
+  size_t lds = 0;
+  const bool multi = plans[0]->vec16;
+  *common = Tile{4, 1, 1, 0};
+  if (!multi) {
+    std::vector<Tile> cand;
+    for (int i = 0; i < n; ++i) cand.push_back(plans[i]->tile);
+    std::stable_sort(cand.begin(), cand.end(),
+                     [](const Tile& a, const Tile& b) { return a.nbt > b.nbt; });
+    for (const Tile& c : cand) {
+      bool ok = true;
+      for (int i = 0; i < n && ok; ++i) ok = tile_ok(plans[i], c);
+      if (ok) {
+        *common = c;
+        break;
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    bf_plan_s tmp = *plans[i];  // the same set under its launch tile
+    Tile t = *common;
+    int variant = -1;
+    if (multi) {
+      const int nm = (int)(sizeof(kMultiTiles) / sizeof(kMultiTiles[0]));
+      auto fits = [&](const Tile& c) {
+        return tile_ok(&tmp, c) && lds_bytes(tmp.prec, tmp.Kpad, c.nbt) <= lds_cap;
+      };
+      for (int v = 0; v < nm && variant < 0; ++v) {
+        const Tile& c = kMultiTiles[v];
+        if (c.mt == tmp.tile.mt && c.nbt == tmp.tile.nbt && c.nbp == tmp.tile.nbp &&
+            c.kres == tmp.tile.kres && fits(c))
+          variant = v;
+      }
+      for (int v = 0; v < nm && variant < 0; ++v)
+        if (fits(kMultiTiles[v]) && kMultiTiles[v].kres == tmp.tile.kres &&
+            kMultiTiles[v].nbt <= tmp.tile.nbt)
+          variant = v;
+      for (int v = 0; v < nm && variant < 0; ++v)
+        if (fits(kMultiTiles[v])) variant = v;
+      if (variant < 0) return BF_ERR_UNSUPPORTED;
+      t = kMultiTiles[variant];
+    }
+    int32_t G, QI, SG;
+    schedule(tmp.I, tmp.T, &G, &QI, &SG);
+    const int32_t base = t.mt / gcd(t.mt, G);
+    const bool same = t.mt == tmp.tile.mt && t.nbt == tmp.tile.nbt && t.nbp == tmp.tile.nbp &&
+                      t.kres == tmp.tile.kres;
+    tmp.tile = t;
+    tmp.sgw = same ? tmp.sgw : std::max(base, tmp.sgw / base * base);
+    L->prob[i] = make_prob(&tmp, x[i], out[i], begin);
+    L->prob[i].variant = variant;
+    begin += units_for(&tmp, t, tmp.sgw);
+    lds = std::max(lds, lds_bytes(tmp.prec, tmp.Kpad, t.nbt));
+  }
+  if (lds > lds_cap) return BF_ERR_UNSUPPORTED;
+  L->nprob = n;
+  L->total_units = begin;
+  L->xcd_remap = 0;
+  *lds_out = lds;
+  return BF_OK;
+}
 
 }  // namespace
 
@@ -544,87 +630,29 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
   try {
     if (!bt || !x || !out) return BF_ERR_INVALID_ARG;
     const int n = (int)bt->plans.size();
-    for (int i = 0; i < n; ++i) {
-      const bf_plan_s* p = bt->plans[i];
-      if (!x[i] || !out[i] || !aligned16(x[i]) || !aligned16(out[i])) return BF_ERR_INVALID_ARG;
-      if (!p->weights_set) return BF_ERR_STATE;
-    }
     Launch L;
-    std::memset(&L, 0, sizeof(L));
-    int64_t begin = 0;
     size_t lds = 0;
-    const bool multi = bt->plans[0]->vec16;
     Tile common{4, 1, 1, 0};
-    if (!multi) {
-      // byte-load (2N % 16 != 0) sets: one generic variant for all
-      std::vector<Tile> cand;
-      for (int i = 0; i < n; ++i) cand.push_back(bt->plans[i]->tile);
-      std::stable_sort(cand.begin(), cand.end(),
-                       [](const Tile& a, const Tile& b) { return a.nbt > b.nbt; });
-      for (const Tile& c : cand) {
-        bool ok = true;
-        for (int i = 0; i < n && ok; ++i) ok = tile_ok(bt->plans[i], c);
-        if (ok) {
-          common = c;
-          break;
-        }
-      }
-    }
-    for (int i = 0; i < n; ++i) {
-      bf_plan_s tmp = *bt->plans[i];  // the same set under its launch tile
-      Tile t = common;
-      int variant = -1;
-      if (multi) {
-        // the set's own tile if the batching kernel carries it, else the
-        // multi variant closest to it (same K residency, largest beam range)
-        const int nm = (int)(sizeof(kMultiTiles) / sizeof(kMultiTiles[0]));
-        for (int v = 0; v < nm && variant < 0; ++v) {
-          const Tile& c = kMultiTiles[v];
-          if (c.mt == tmp.tile.mt && c.nbt == tmp.tile.nbt && c.nbp == tmp.tile.nbp &&
-              c.kres == tmp.tile.kres && tile_ok(&tmp, c))
-            variant = v;
-        }
-        for (int v = 0; v < nm && variant < 0; ++v)
-          if (tile_ok(&tmp, kMultiTiles[v]) && kMultiTiles[v].kres == tmp.tile.kres &&
-              kMultiTiles[v].nbt <= tmp.tile.nbt)
-            variant = v;
-        for (int v = 0; v < nm && variant < 0; ++v)
-          if (tile_ok(&tmp, kMultiTiles[v])) variant = v;
-        if (variant < 0) return BF_ERR_UNSUPPORTED;
-        t = kMultiTiles[variant];
-      }
-      int32_t G, QI, SG;
-      schedule(tmp.I, tmp.T, &G, &QI, &SG);
-      const int32_t base = t.mt / gcd(t.mt, G);
-      const bool same = t.mt == tmp.tile.mt && t.nbt == tmp.tile.nbt && t.nbp == tmp.tile.nbp &&
-                        t.kres == tmp.tile.kres;
-      tmp.tile = t;
-      tmp.sgw = same ? tmp.sgw : std::max(base, tmp.sgw / base * base);
-      L.prob[i] = make_prob(&tmp, x[i], out[i], begin);
-      L.prob[i].variant = variant;
-      begin += units_for(&tmp, t, tmp.sgw);
-      lds = std::max(lds, lds_bytes(tmp.prec, tmp.Kpad, t.nbt));
-    }
-    if (lds > kLdsMax) return BF_ERR_UNSUPPORTED;
-    L.nprob = n;
-    L.total_units = begin;
+    const int st = fill_sets(bt->plans.data(), n, x, out, kLdsMax, &L, &lds, &common);
+    if (st != BF_OK) return st;
     L.queue = bt->queue;
-    L.xcd_remap = 0;
     const bf_plan_s* p0 = bt->plans[0];
+    const bool multi = p0->vec16;
     int per_cu = lds <= 80 * 1024 ? 2 : 1;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
     if (multi) {
       int occ = 0;
-      e = bf::launch_beamform_multi(p0->prec, p0->mode, L, 0, lds, s, &occ);
+      e = bf::launch_beamform_multi(p0->prec, p0->mode, L, nullptr, 0, lds, s, &occ);
       if (e != hipSuccess) return from_hip(e);
       per_cu = std::max(1, occ);
     }
-    int64_t grid = std::min<int64_t>(begin, (int64_t)p0->n_cu * per_cu);
+    int64_t grid = std::min<int64_t>(L.total_units, (int64_t)p0->n_cu * per_cu);
     if (grid < 1) grid = 1;
     e = bf::launch_queue_reset(bt->queue, s);
     if (e == hipSuccess) {
-      e = multi ? bf::launch_beamform_multi(p0->prec, p0->mode, L, (int)grid, lds, s, nullptr)
+      e = multi ? bf::launch_beamform_multi(p0->prec, p0->mode, L, nullptr, (int)grid, lds, s,
+                                            nullptr)
                 : bf::launch_beamform(p0->prec, p0->mode, p0->vec16, common, L, (int)grid, lds, s);
     }
     return from_hip(e);
@@ -641,6 +669,102 @@ int bf_batch_destroy(bf_batch_t bt) {
   return BF_OK;
 }
 
+int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, int32_t precision) {
+  try {
+    if (!out) return BF_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n_antennas < 1 || n_antennas > kMaxN || integration < 1) return BF_ERR_INVALID_ARG;
+    if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
+      return BF_ERR_INVALID_ARG;
+    if ((2 * n_antennas) % 16 != 0) return BF_ERR_UNSUPPORTED;
+    bf_table_s* t = new bf_table_s();
+    t->N = n_antennas;
+    t->I = integration;
+    t->prec = precision;
+    t->mode = mode_of(integration);
+    t->Kpad = 64 * ((2 * n_antennas + 63) / 64);
+    // one LDS size for every launch: the largest batching variant that still
+    // leaves two workgroups per CU (at least the smallest variant)
+    t->lds = lds_bytes(precision, t->Kpad, 1);
+    for (const Tile& c : kMultiTiles) {
+      const size_t l = lds_bytes(precision, t->Kpad, c.nbt);
+      if (l <= 80 * 1024) t->lds = std::max(t->lds, l);
+    }
+    if (t->lds > kLdsMax) {
+      delete t;
+      return BF_ERR_UNSUPPORTED;
+    }
+    hipError_t e = hipGetDevice(&t->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&t->n_cu, hipDeviceAttributeMultiprocessorCount,
+                                                   t->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&t->queue, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&t->table, sizeof(Launch));
+    int occ = 0;
+    if (e == hipSuccess) {
+      Launch L;
+      std::memset(&L, 0, sizeof(L));
+      e = bf::launch_beamform_multi(precision, t->mode, L, t->table, 0, t->lds, nullptr, &occ);
+    }
+    if (e != hipSuccess) {
+      if (t->queue) (void)hipFree(t->queue);
+      if (t->table) (void)hipFree(t->table);
+      delete t;
+      return from_hip(e);
+    }
+    t->grid = std::max(1, t->n_cu * std::max(1, occ));
+    *out = t;
+    return BF_OK;
+  } catch (...) {
+    return BF_ERR_OOM;
+  }
+}
+
+int bf_table_set(bf_table_t t, const bf_plan_t* plans, const int8_t* const* x, float* const* out,
+                 int32_t n, void* stream) {
+  try {
+    if (!t || n < 0 || (n > 0 && (!plans || !x || !out))) return BF_ERR_INVALID_ARG;
+    if (n > bf::kMaxProbs) return BF_ERR_UNSUPPORTED;
+    for (int i = 0; i < n; ++i) {
+      const bf_plan_s* p = plans[i];
+      if (!p) return BF_ERR_INVALID_ARG;
+      if (p->N != t->N || p->I != t->I || p->prec != t->prec || p->device != t->device)
+        return BF_ERR_UNSUPPORTED;
+    }
+    Launch L;
+    std::memset(&L, 0, sizeof(L));
+    if (n > 0) {
+      size_t lds = 0;
+      Tile common{4, 1, 1, 0};
+      const int st = fill_sets(plans, n, x, out, t->lds, &L, &lds, &common);
+      if (st != BF_OK) return st;
+    }
+    L.queue = t->queue;
+    return from_hip(bf::launch_table_store(L, t->table, reinterpret_cast<hipStream_t>(stream)));
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
+int bf_table_run(bf_table_t t, void* stream) {
+  if (!t) return BF_ERR_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Launch unused;
+  std::memset(&unused, 0, sizeof(unused));
+  hipError_t e = bf::launch_queue_reset(t->queue, s);
+  if (e == hipSuccess)
+    e = bf::launch_beamform_multi(t->prec, t->mode, unused, t->table, t->grid, t->lds, s, nullptr);
+  return from_hip(e);
+}
+
+int bf_table_destroy(bf_table_t t) {
+  if (!t) return BF_OK;
+  (void)hipDeviceSynchronize();
+  if (t->queue) (void)hipFree(t->queue);
+  if (t->table) (void)hipFree(t->table);
+  delete t;
+  return BF_OK;
+}
+
 }  // extern "C"
 
 namespace bf {
@@ -653,17 +777,20 @@ extern template hipError_t launch_prec<1>(int, bool, Tile, const Launch&, int, s
 extern template hipError_t launch_prec<2>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
 
 template <int PREC>
-hipError_t launch_multi_prec(int mode, const Launch& L, int grid, size_t lds, hipStream_t s,
-                             int* occupancy);
-extern template hipError_t launch_multi_prec<0>(int, const Launch&, int, size_t, hipStream_t, int*);
-extern template hipError_t launch_multi_prec<1>(int, const Launch&, int, size_t, hipStream_t, int*);
-extern template hipError_t launch_multi_prec<2>(int, const Launch&, int, size_t, hipStream_t, int*);
+hipError_t launch_multi_prec(int mode, const Launch& L, const Launch* table, int grid, size_t lds,
+                             hipStream_t s, int* occupancy);
+extern template hipError_t launch_multi_prec<0>(int, const Launch&, const Launch*, int, size_t,
+                                                hipStream_t, int*);
+extern template hipError_t launch_multi_prec<1>(int, const Launch&, const Launch*, int, size_t,
+                                                hipStream_t, int*);
+extern template hipError_t launch_multi_prec<2>(int, const Launch&, const Launch*, int, size_t,
+                                                hipStream_t, int*);
 
-hipError_t launch_beamform_multi(int prec, int mode, const Launch& L, int grid, size_t lds_bytes,
-                                 hipStream_t stream, int* occupancy) {
-  if (prec == 0) return launch_multi_prec<0>(mode, L, grid, lds_bytes, stream, occupancy);
-  if (prec == 1) return launch_multi_prec<1>(mode, L, grid, lds_bytes, stream, occupancy);
-  return launch_multi_prec<2>(mode, L, grid, lds_bytes, stream, occupancy);
+hipError_t launch_beamform_multi(int prec, int mode, const Launch& L, const Launch* table,
+                                 int grid, size_t lds_bytes, hipStream_t stream, int* occupancy) {
+  if (prec == 0) return launch_multi_prec<0>(mode, L, table, grid, lds_bytes, stream, occupancy);
+  if (prec == 1) return launch_multi_prec<1>(mode, L, table, grid, lds_bytes, stream, occupancy);
+  return launch_multi_prec<2>(mode, L, table, grid, lds_bytes, stream, occupancy);
 }
 
 hipError_t launch_beamform(int prec, int mode, bool vec16, Tile tile, const Launch& L, int grid,

@@ -4,5 +4,6 @@
 
 namespace bf {
 template hipError_t launch_prec<1>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
-template hipError_t launch_multi_prec<1>(int, const Launch&, int, size_t, hipStream_t, int*);
+template hipError_t launch_multi_prec<1>(int, const Launch&, const Launch*, int, size_t,
+                                            hipStream_t, int*);
 }

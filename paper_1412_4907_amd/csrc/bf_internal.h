@@ -74,10 +74,11 @@ struct Tile {
 // Returns hipSuccess or the launch error.
 hipError_t launch_beamform(int prec, int mode, bool vec16, Tile tile, const Launch& L,
                            int grid, size_t lds_bytes, hipStream_t stream);
-// Persistent batching kernel (per-set variants); occupancy != null only
-// queries workgroups per CU.
-hipError_t launch_beamform_multi(int prec, int mode, const Launch& L, int grid, size_t lds_bytes,
-                                 hipStream_t stream, int* occupancy);
+// Persistent batching kernel (per-set variants).  table != null: the form
+// that reads its set table from that device copy (L unused).
+// occupancy != null only queries workgroups per CU.
+hipError_t launch_beamform_multi(int prec, int mode, const Launch& L, const Launch* table,
+                                 int grid, size_t lds_bytes, hipStream_t stream, int* occupancy);
 
 hipError_t launch_weights_geom(int prec, const double* pos, const double* dir,
                                const double* freq, int N, int C, int B, int Bpad, int Kpad,
@@ -85,5 +86,8 @@ hipError_t launch_weights_geom(int prec, const double* pos, const double* dir,
 hipError_t launch_weights_raw(int prec, const double* wraw, int N, int C, int B, int Bpad,
                               int Kpad, void* w, hipStream_t stream);
 hipError_t launch_queue_reset(int32_t* q, hipStream_t stream);
+// Stores a set table into device memory (one workgroup, vector stores), in
+// stream order before the table kernel that reads it.
+hipError_t launch_table_store(const Launch& L, Launch* dst, hipStream_t stream);
 
 }  // namespace bf

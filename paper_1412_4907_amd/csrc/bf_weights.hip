@@ -139,6 +139,15 @@ __global__ void weights_raw_kernel(const double* __restrict__ wraw, int N, int C
 
 __global__ void queue_reset_kernel(int32_t* q) { *q = 0; }
 
+// Copies a set table from the kernel arguments into device memory, one dword
+// per thread per step.
+__global__ void __launch_bounds__(kThreads) table_store_kernel(const Launch L, Launch* dst) {
+  static_assert(sizeof(Launch) % 4 == 0, "the table is copied in dwords");
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&L);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(Launch) / 4); i += kThreads) d[i] = src[i];
+}
+
 static int grid_for(int64_t total) {
   int64_t g = (total + 255) / 256;
   return (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
@@ -171,6 +180,10 @@ hipError_t launch_weights_raw(int prec, const double* wraw, int N, int C, int B,
 
 hipError_t launch_queue_reset(int32_t* q, hipStream_t s) {
   return launch(queue_reset_kernel, 1, 1, s, q);
+}
+
+hipError_t launch_table_store(const Launch& L, Launch* dst, hipStream_t s) {
+  return launch(table_store_kernel, 1, kThreads, s, L, dst);
 }
 
 }  // namespace bf

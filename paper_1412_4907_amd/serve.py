@@ -18,9 +18,11 @@ builds those ideas on one MI355X:
   next block's launch (continuous batching, not a queue of whole jobs);
 * each admitted request owns a plan (weights generated on the device once,
   at admission) and two output buffers; integration state never leaves HBM;
-* the per-block work for the active set -- one queue-reset kernel and one
-  persistent beamform launch over every active request -- is captured once
-  per (active set, ring slot) as a hipGraph and replayed;
+* the per-block work -- one queue-reset kernel and one persistent beamform
+  launch over every active request -- reads its set table (which requests,
+  which ring slot, which output buffers) from device memory, so it is
+  captured once as a hipGraph and replayed for every block; before each
+  replay a one-workgroup kernel stores that block's table;
 * per block: arrival time, completion event, latency, and the real-time
   factor (block period / processing time) are recorded.
 
@@ -150,8 +152,9 @@ class Scheduler:
 
 
 class GpuExecutor:
-    """Runs the per-block batched launch through the C ABI, as a hipGraph
-    per (active set, ring slot)."""
+    """Runs the per-block batched launch through the C ABI: a table batch
+    whose launch is captured once as a hipGraph and replayed for every
+    block, whatever the active set."""
 
     def __init__(self, pos: np.ndarray, freqs: np.ndarray, n_samples: int, integration: int,
                  precision: str = "fp16", ring: Sequence = (), use_graphs: bool = True):
@@ -167,8 +170,8 @@ class GpuExecutor:
         self.stream = torch.cuda.Stream()
         self.plans: Dict[int, object] = {}
         self.outs: Dict[int, List] = {}
-        self.graphs: Dict[tuple, object] = {}
-        self.batches: Dict[tuple, object] = {}
+        self.table = bf.Table(self.N, self.I, precision)
+        self.graph = None
         self.graveyard: List = []
         self.graveyard_outs: List = []
         self.graveyard_held = 0
@@ -189,12 +192,9 @@ class GpuExecutor:
 
     def retire(self, r: Request) -> None:
         """Drop a request.  Freeing device memory synchronises the device,
-        so plans, batches and outputs go to a graveyard that is emptied
-        when it grows past ``graveyard_bytes`` or at close()."""
-        for k in [k for k in self.graphs if r.rid in k[0]]:
-            del self.graphs[k]
-        for k in [k for k in self.batches if r.rid in k]:
-            self.graveyard.append(self.batches.pop(k))
+        so plans and outputs go to a graveyard that is emptied when it grows
+        past ``graveyard_bytes`` or at close(); a retired request is left out
+        of every later table."""
         outs = self.outs.pop(r.rid, None)
         p = self.plans.pop(r.rid, None)
         if p is not None:
@@ -212,41 +212,28 @@ class GpuExecutor:
         self.graveyard_outs.clear()
         self.graveyard_held = 0
 
-    def _batch(self, ids: tuple):
-        b = self.batches.get(ids)
-        if b is None:
-            b = self.bf.Batch([self.plans[i] for i in ids])
-            self.batches[ids] = b
-        return b
-
-    def _launch(self, ids: tuple, slot: int, parity: int) -> None:
-        b = self._batch(ids)
-        xs = [self.ring[slot]] * len(ids)
-        ps = [self.outs[i][parity] for i in ids]
-        b.run(xs, ps, stream=self.stream)
-
     def run_block(self, ids: Sequence[int], slot: int, parity: int):
         """Enqueue one block's work on the serve stream; returns an event
         recorded after it."""
         torch = self.torch
         ids = tuple(sorted(ids))
         if ids:
-            key = (ids, slot, parity)
-            g = self.graphs.get(key) if self.use_graphs else None
-            if g is None:
-                # first use of this active set: run eagerly (also the warm-up
-                # that keeps one-time runtime calls out of the capture), then
-                # capture the same launch for later blocks
-                self._launch(ids, slot, parity)
+            self.table.set([self.plans[i] for i in ids], [self.ring[slot]] * len(ids),
+                           [self.outs[i][parity] for i in ids], stream=self.stream)
+            if self.graph is None or not self.use_graphs:
+                # first block: run eagerly (also the warm-up that keeps
+                # one-time runtime calls out of the capture), then capture
+                # the same launch for every later block
+                self.table.run(stream=self.stream)
                 self.eager_launches += 1
                 if self.use_graphs:
                     g = torch.cuda.CUDAGraph()
                     with torch.cuda.graph(g, stream=self.stream):
-                        self._launch(ids, slot, parity)
-                    self.graphs[key] = g
+                        self.table.run(stream=self.stream)
+                    self.graph = g
             else:
                 with torch.cuda.stream(self.stream):
-                    g.replay()
+                    self.graph.replay()
                 self.graph_replays += 1
         ev = torch.cuda.Event()
         ev.record(self.stream)
@@ -257,9 +244,8 @@ class GpuExecutor:
 
     def close(self) -> None:
         self.stream.synchronize()
-        self.graphs.clear()
-        for k in list(self.batches):
-            self.batches.pop(k).destroy()
+        self.graph = None
+        self.table.destroy()
         for p in self.plans.values():
             p.destroy()
         self.plans.clear()
@@ -268,11 +254,14 @@ class GpuExecutor:
 
 
 def serve(executor, scheduler: Scheduler, requests: Sequence[Request], n_blocks: int,
-          block_period_s: float, pace: float = 0.0, on_block=None) -> List[BlockRecord]:
-    """Run ``n_blocks`` blocks.  ``pace`` > 0 releases block k at
-    k * block_period_s / pace seconds after start (a replay ``pace`` times
-    faster than real time); 0 releases each block as soon as its ring slot is
-    free.  Returns one record per block (latency = release -> completion)."""
+          block_period_s: float, pace: float = 0.0, on_block=None,
+          arrivals: Optional[Sequence[float]] = None) -> List[BlockRecord]:
+    """Run ``n_blocks`` blocks.  ``arrivals`` (seconds from the start, e.g.
+    a Poisson process) releases block k at arrivals[k]; else ``pace`` > 0
+    releases it at k * block_period_s / pace (a replay ``pace`` times faster
+    than real time), and 0 releases each block as soon as its ring slot is
+    free.  Returns one record per block (latency = release -> completion, so
+    a block that arrives while earlier ones still run includes its wait)."""
     pending = sorted(requests, key=lambda r: r.arrival_block)
     pi = 0
     records: List[BlockRecord] = []
@@ -296,13 +285,19 @@ def serve(executor, scheduler: Scheduler, requests: Sequence[Request], n_blocks:
             ev, rec = inflight.pop(0)
             ev.synchronize()
             rec.done_s = time.perf_counter() - t0
-        if pace > 0:
+        release = None
+        if arrivals is not None:
+            release = float(arrivals[k])
+        elif pace > 0:
             release = k * block_period_s / pace
-            now = time.perf_counter() - t0
-            if release > now:
-                time.sleep(release - now)
+        now = time.perf_counter() - t0
+        if release is not None and release > now:
+            time.sleep(release - now)
+        # latency counts from the block's arrival (it may have waited for a
+        # ring slot behind earlier blocks)
+        arrived = release if release is not None else time.perf_counter() - t0
         rec = BlockRecord(k, sorted(scheduler.active), sum(r.n_beams for r in scheduler.active.values()),
-                          time.perf_counter() - t0)
+                          arrived)
         ev = executor.run_block(rec.active, k % n_slots, k & 1)
         inflight.append((ev, rec))
         records.append(rec)

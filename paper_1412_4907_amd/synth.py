@@ -289,6 +289,14 @@ def serve_block(block: int, n_chan: int = 1024, n_samples: int = 8192) -> Worklo
                     pos, np.zeros((0, 3)), channel_freqs(n_chan, 400e6, 16e6))
 
 
+def serve_block_arrivals(n_blocks: int, period_s: float, pace: float = 1.0) -> np.ndarray:
+    """Seeded Poisson arrival times (seconds from the start) of the serving
+    form's voltage blocks: exponential gaps with mean ``period_s / pace``
+    (a replay ``pace`` times faster than real time)."""
+    g = rng("serve", "blocks")
+    return np.cumsum(g.exponential(period_s / pace, n_blocks)) - 0.0
+
+
 def serve_requests(n: int, mean_concurrent_beams: float = 512.0, mean_lifetime: float = 4.0):
     """Seeded beam-set requests for the serving form: Poisson arrivals (in
     block units), beams log-uniform over 64..2048, lifetimes geometric with

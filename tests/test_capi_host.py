@@ -54,6 +54,15 @@ def test_validation_before_any_device_call():
     assert L.bf_plan_destroy(None) == bf.OK
     assert L.bf_batch_destroy(None) == bf.OK
     assert L.bf_batch_create(None, None, 1) == bf.ERR_INVALID_ARG
+    # table batch: sizes, precision and 16-byte rows are checked first
+    assert L.bf_table_create(None, 32, 16, 1) == bf.ERR_INVALID_ARG
+    assert L.bf_table_create(ctypes.byref(h), 0, 16, 1) == bf.ERR_INVALID_ARG
+    assert L.bf_table_create(ctypes.byref(h), 32, 0, 1) == bf.ERR_INVALID_ARG
+    assert L.bf_table_create(ctypes.byref(h), 32, 16, 5) == bf.ERR_INVALID_ARG
+    assert L.bf_table_create(ctypes.byref(h), 33, 16, 1) == bf.ERR_UNSUPPORTED
+    assert L.bf_table_set(None, None, None, None, 0, None) == bf.ERR_INVALID_ARG
+    assert L.bf_table_run(None, None) == bf.ERR_INVALID_ARG
+    assert L.bf_table_destroy(None) == bf.OK
 
 
 def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
