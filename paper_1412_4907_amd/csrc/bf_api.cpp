@@ -199,6 +199,10 @@ Prob make_prob(const bf_plan_s* p, const int8_t* x, float* out, int64_t unit_beg
   q.ntr = (int32_t)((SG + (int64_t)bf::kWaves * p->sgw - 1) / ((int64_t)bf::kWaves * p->sgw));
   q.accumulate = (p->flags & BF_ACCUMULATE) ? 1 : 0;
   q.variant = -1;
+  // several beam ranges per channel: a time range's voltage rows (its
+  // share of the channel block) serve every beam range from L2 if those
+  // units run together, whereas one beam range's weights are small
+  q.br_fast = q.nbr > 1 ? 1 : 0;
   return q;
 }
 

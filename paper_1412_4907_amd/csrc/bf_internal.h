@@ -37,6 +37,9 @@ struct Prob {
   int32_t SG;         // store groups per channel
   int32_t accumulate; // add into P instead of overwriting
   int32_t variant;    // multi-variant launches: index into BF_TILE_LIST_MULTI
+  int32_t br_fast;    // unit order (c, tr, br) instead of (c, br, tr): the beam
+                      // ranges of one time range run back to back and share its
+                      // voltages through L2
 };
 
 struct Launch {
