@@ -50,7 +50,39 @@ def parse():
                     help="serve: HBM budget for admitted requests")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run device-to-device copies of BYTES (counter calibration)")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="only time the vendor GEMM (torch.matmul, random data) at a few sizes: "
+                         "the device's practical dense rate, for context")
     return ap.parse_args()
+
+
+def library_gemm(reps: int = 30) -> None:
+    """Median TFLOP/s of torch.matmul (hipBLASLt on ROCm) on random data:
+    the practical dense-GEMM rate of this device under sustained load."""
+    import torch
+    dev = torch.device("cuda:0")
+    rows = []
+    for dtype, (m, n, k) in ((torch.float16, (8192, 8192, 8192)), (torch.float16, (16384, 16384, 8192)),
+                             (torch.bfloat16, (8192, 8192, 8192)), (torch.float32, (8192, 8192, 8192))):
+        a = torch.randn(m, k, device=dev, dtype=dtype)
+        b = torch.randn(k, n, device=dev, dtype=dtype)
+        for _ in range(3):
+            a @ b
+        torch.cuda.synchronize()
+        r = reps if dtype != torch.float32 else 10
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(r + 1)]
+        ev[0].record()
+        for i in range(r):
+            a @ b
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(r))
+        rows.append({"dtype": str(dtype).split(".")[-1], "m": m, "n": n, "k": k,
+                     "median_ms": round(ms[r // 2], 4),
+                     "tflops_median": round(2.0 * m * n * k / ms[r // 2] / 1e9, 1),
+                     "tflops_best": round(2.0 * m * n * k / ms[0] / 1e9, 1)})
+        del a, b
+    print(json.dumps({"library_gemm": rows}), flush=True)
 
 
 def copy_calibration(nbytes: int, reps: int = 3) -> None:
@@ -301,6 +333,9 @@ def main():
     a = parse()
     if a.copy_calibration:
         copy_calibration(a.copy_calibration)
+        return
+    if a.library_gemm:
+        library_gemm()
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
