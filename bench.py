@@ -114,17 +114,21 @@ def algorithmic_bytes(w, prec) -> float:
 
 def time_plan(plan, xd, p, steps, warmup, torch):
     """Per-step HIP events on torch's current stream (the stream bf_run is
-    given); returns per-step ms and the whole timed region in ms."""
+    given); returns per-step ms and the whole timed region in ms.  xd and p
+    may be lists of equally shaped buffers, used in turn (so that a small
+    workload cannot be served from the 256 MB last-level cache)."""
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
-    xp, pp = xd.data_ptr(), p.data_ptr()
-    for _ in range(warmup):
-        plan.run_ptr(xp, pp, sp)
+    xs = xd if isinstance(xd, (list, tuple)) else [xd]
+    ps = p if isinstance(p, (list, tuple)) else [p]
+    bufs = [(x.data_ptr(), q.data_ptr()) for x, q in zip(xs, ps)]
+    for i in range(warmup):
+        plan.run_ptr(*bufs[i % len(bufs)], sp)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record(stream)
     for i in range(steps):
-        plan.run_ptr(xp, pp, sp)
+        plan.run_ptr(*bufs[i % len(bufs)], sp)
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
@@ -189,6 +193,23 @@ def precision_report(torch, dev, n_chan_check: int = 5) -> dict:
     return rep
 
 
+def roofline(tflops: float, peak: float, abytes: float, ms: float, flops: float, traffic) -> dict:
+    """The bounding roofline of the workload: MFMA when its arithmetic
+    intensity (flop per algorithmic byte) is above the ridge peak / 8 TB/s,
+    else HBM; achieved and peak in that roofline's unit."""
+    gbs = abytes / (ms * 1e-3) / 1e9
+    ridge = peak * 1e12 / (PEAK_HBM_GBS * 1e9)
+    common = {"traffic": traffic, "algorithmic_bytes": abytes, "intensity_flop_per_byte":
+              round(flops / abytes, 1), "ridge_flop_per_byte": round(ridge, 1)}
+    if flops / abytes >= ridge:
+        return {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(tflops / peak, 4), **common,
+                "algorithmic_hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), **common,
+            "mfma_tflops": round(tflops, 3), "mfma_frac": round(tflops / peak, 4)}
+
+
 def load_traffic(kernel_key: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel build (else null)."""
@@ -210,10 +231,16 @@ def serve_bench(a, torch, dev):
     """Serving form: 256-antenna 16x16 array, blocks of 1024 channels x 8192
     samples (524.288 ms each), FP16, I=64, seeded Poisson beam-set requests
     (64..2048 beams, mean ~512 concurrently active) admitted by HBM footprint,
-    one batched launch per block replayed as a hipGraph.  Two runs: as fast as
-    the ring allows (throughput, real-time factor) and with seeded Poisson
-    block arrivals at ``--pace``x real time (block latency p50/p99, arrival to
-    completion)."""
+    one batched launch per block replayed as a hipGraph.  Runs:
+    * throughput: blocks pre-staged in an HBM ring (the NIC-to-GPU case),
+      released as soon as a ring slot frees -> real-time factor;
+    * paced: seeded Poisson block arrivals at ``--pace``x real time -> block
+      latency p50/p99 from arrival to completion;
+    * h2d: as throughput, but every block first copied from pinned host
+      memory on a second stream, overlapped with the previous block's compute
+      (PCIe-bound context, never the headline value);
+    * load curve: real-time factor against the mean number of concurrently
+      active beams (shorter runs)."""
     from paper_1412_4907_amd import serve, synth
     prec = "fp16" if a.precision == "fp32" else a.precision
     pos = synth.serve_array()
@@ -226,7 +253,6 @@ def serve_bench(a, torch, dev):
         blk = synth.serve_block(k)
         ring.append(torch.from_numpy(blk.voltages(workers=16)).to(dev))
     gen_s = time.perf_counter() - t0
-    reqs_spec = synth.serve_requests(64)
     fp = lambda r: serve.footprint_bytes(r.n_beams, 256, C, T, I, prec)  # noqa: E731
     budget = int(a.serve_budget_gb * (1 << 30))
     out = {"metric": "beamforming TFLOP/s (8 flop/cMAC) + % MFMA peak; real-time factor, "
@@ -238,14 +264,14 @@ def serve_bench(a, torch, dev):
                       "ring_slots": len(ring), "blocks": a.blocks,
                       "paced_arrivals": f"seeded Poisson, mean gap {period / a.pace * 1e3:.3f} ms "
                                         f"({a.pace:g}x real time)"}}
-    arrivals = synth.serve_block_arrivals(a.blocks, period, a.pace)
-    for mode, arr in (("throughput", None), ("paced", arrivals)):
+
+    def run(reqs_spec, n_blocks, arrivals=None, host_blocks=None):
         reqs = [serve.Request(i, d, lifetime=life, arrival_block=arr_b)
                 for i, (arr_b, nb, life, d) in enumerate(reqs_spec)]
-        ex = serve.GpuExecutor(pos, freqs, T, I, prec, ring=ring)
+        ex = serve.GpuExecutor(pos, freqs, T, I, prec, ring=ring, host_blocks=host_blocks)
         sch = serve.Scheduler(budget, fp)
-        recs = serve.serve(ex, sch, reqs, n_blocks=a.blocks, block_period_s=period,
-                           arrivals=arr)
+        recs = serve.serve(ex, sch, reqs, n_blocks=n_blocks, block_period_s=period,
+                           arrivals=arrivals)
         ex.close()
         st = serve.summarize(recs, period)
         beams = sum(r.beams for r in recs)
@@ -253,7 +279,27 @@ def serve_bench(a, torch, dev):
         st["graph_replays"] = ex.graph_replays
         st["eager_launches"] = ex.eager_launches
         st["requests_finished"] = len(sch.finished)
-        out[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+        if host_blocks is not None:
+            st["h2d_gb_s"] = ex.h2d_bytes / st["wall_s"] / 1e9 if st["wall_s"] else None
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+
+    reqs_spec = synth.serve_requests(64)
+    out["throughput"] = run(reqs_spec, a.blocks)
+    out["paced"] = run(reqs_spec, a.blocks, arrivals=synth.serve_block_arrivals(a.blocks, period,
+                                                                                 a.pace))
+    host = []
+    for r in ring:
+        h = torch.empty(r.shape, dtype=r.dtype, pin_memory=True)
+        h.copy_(r)
+        host.append(h)
+    out["h2d"] = run(reqs_spec, min(a.blocks, 60), host_blocks=host)
+    del host
+    curve = []
+    for load in (128, 256, 512, 1024, 2048):
+        st = run(synth.serve_requests(64, mean_concurrent_beams=float(load)), min(a.blocks, 100))
+        curve.append({"mean_concurrent_beams": load, "mean_active_beams": st["mean_active_beams"],
+                      "rtf": st["rtf"], "tflops": st["tflops"], "p99_block_ms": st["p99_block_ms"]})
+    out["rtf_vs_load"] = curve
     thr = out["throughput"]
     out["value"] = round(thr["tflops"], 3)
     out["mfma_peak_frac"] = round(thr["tflops"] / PEAK_TFLOPS[prec], 4)
@@ -365,8 +411,21 @@ def main():
         # tile shape from the autotuner's cache, else tuned now (untimed)
         if a.retune or tune.apply_cached(plan) is None:
             tune.tune(plan, xd, p, reps=3)
-        per, total = time_plan(plan, xd, p, steps, warmup, torch)
+        hot = None
+        if xd.numel() + p.numel() * 4 < (1 << 30):
+            # small footprint: 16 distinct input/output buffers in turn, so
+            # the timed figure is not served from the last-level cache; the
+            # single-buffer ("hot") figure is reported beside it
+            xs = [xd] + [xd.clone() for _ in range(15)]
+            ps = [p] + [torch.empty_like(p) for _ in range(15)]
+            per, total = time_plan(plan, xs, ps, steps, warmup, torch)
+            _, hot_total = time_plan(plan, xd, p, steps, warmup, torch)
+            hot = hot_total / steps
+            del xs, ps
+        else:
+            per, total = time_plan(plan, xd, p, steps, warmup, torch)
         info = plan.info()
+        info["hot_ms"] = hot
         plan.destroy()
         del p
         return per, total, info
@@ -403,17 +462,17 @@ def main():
                    "work_units": info["work_units"]},
         "mfma_peak_frac": round(value / peak, 4),
         "real_time_factor": round(block_s / (ms * 1e-3), 1),
+        "p10_block_ms": round(float(np.percentile(per, 10)), 4),
         "p50_block_ms": round(float(np.percentile(per, 50)), 4),
+        "p90_block_ms": round(float(np.percentile(per, 90)), 4),
         "p99_block_ms": round(float(np.percentile(per, 99)), 4),
         "block_period_ms": round(block_s * 1e3, 3),
-        "roofline": {"bound": "mfma", "achieved": round(value, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(value / peak, 4),
-                     "traffic": load_traffic(kernel_key),
-                     "algorithmic_bytes": abytes,
-                     "algorithmic_hbm_gbs": round(abytes / (ms * 1e-3) / 1e9, 1),
-                     "hbm_frac": round(abytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+        "roofline": roofline(value, peak, abytes, ms, flops, load_traffic(kernel_key)),
         "input_gen_s": round(gen_s, 1),
     }
+    if info.get("hot_ms") is not None:
+        out["buffers_rotated"] = 16
+        out["hot_ms_per_step"] = round(info["hot_ms"], 4)
     if not a.no_extra:
         extra = {}
         for prec in ("fp32", "fp16", "bf16"):

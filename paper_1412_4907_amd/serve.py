@@ -157,7 +157,8 @@ class GpuExecutor:
     block, whatever the active set."""
 
     def __init__(self, pos: np.ndarray, freqs: np.ndarray, n_samples: int, integration: int,
-                 precision: str = "fp16", ring: Sequence = (), use_graphs: bool = True):
+                 precision: str = "fp16", ring: Sequence = (), use_graphs: bool = True,
+                 host_blocks: Optional[Sequence] = None):
         import torch
         from . import bf, tune
         self.torch, self.bf, self.tune = torch, bf, tune
@@ -168,6 +169,14 @@ class GpuExecutor:
         self.ring = list(ring)           # device int8 [C][T][N][2] tensors
         self.use_graphs = use_graphs
         self.stream = torch.cuda.Stream()
+        # PCIe-fed variant: every block is first copied from pinned host memory
+        # (host_blocks[slot]) into its ring slot on a copy stream; the copy of
+        # a block overlaps the previous block's compute, and a slot is
+        # overwritten only after the compute that read it has finished
+        self.host_blocks = list(host_blocks) if host_blocks is not None else None
+        self.copy_stream = torch.cuda.Stream() if host_blocks is not None else None
+        self.slot_free = [None] * len(self.ring)
+        self.h2d_bytes = 0
         self.plans: Dict[int, object] = {}
         self.outs: Dict[int, List] = {}
         self.table = bf.Table(self.N, self.I, precision)
@@ -217,6 +226,16 @@ class GpuExecutor:
         recorded after it."""
         torch = self.torch
         ids = tuple(sorted(ids))
+        if self.host_blocks is not None:
+            cs = self.copy_stream
+            if self.slot_free[slot] is not None:
+                cs.wait_event(self.slot_free[slot])
+            with torch.cuda.stream(cs):
+                self.ring[slot].copy_(self.host_blocks[slot], non_blocking=True)
+            copied = torch.cuda.Event()
+            copied.record(cs)
+            self.stream.wait_event(copied)
+            self.h2d_bytes += self.ring[slot].numel()
         if ids:
             self.table.set([self.plans[i] for i in ids], [self.ring[slot]] * len(ids),
                            [self.outs[i][parity] for i in ids], stream=self.stream)
@@ -237,6 +256,7 @@ class GpuExecutor:
                 self.graph_replays += 1
         ev = torch.cuda.Event()
         ev.record(self.stream)
+        self.slot_free[slot] = ev
         return ev
 
     def output(self, rid: int, parity: int):
