@@ -72,6 +72,14 @@ enum {
 /* Plan flags. */
 #define BF_ACCUMULATE 1u /* bf_run adds into P instead of overwriting it, so an
                             integration window can span several blocks        */
+/* 4-bit complex voltages (Sec. 2.1: the F-engine emits 4-bit two's
+ * complement components, one antenna sample per byte).  X is then device
+ * uint8 [C][T][N], one byte per antenna sample: the real part in the high
+ * nibble, the imaginary part in the low nibble, each a two's complement
+ * value in [-8, 7]; N must be a multiple of 8 (else BF_ERR_UNSUPPORTED).
+ * The result equals, bit for bit, the int8 form run on the same values
+ * widened to [C][T][N][2].  Half the input bytes of the int8 form. */
+#define BF_INPUT_4BIT 2u
 
 /* Human-readable text for a status code (static storage, never NULL). */
 const char* bf_strerror(int status);
@@ -132,8 +140,9 @@ int bf_set_weights_raw(bf_plan_t plan, const double* weights, void* stream);
 int bf_get_weights(bf_plan_t plan, double* weights_out, void* stream);
 
 /*
- * The hot path: one block.  x_dev: device int8 [C][T][N][2]; p_dev: device
- * float [C][B][T/I]; both 16-byte aligned and not overlapping.  Enqueues
+ * The hot path: one block.  x_dev: device int8 [C][T][N][2] (uint8 [C][T][N]
+ * for a BF_INPUT_4BIT plan); p_dev: device float [C][B][T/I]; both 16-byte
+ * aligned and not overlapping.  Enqueues
  * one kernel on `stream`; no host synchronisation, no allocation.
  * Errors: BF_ERR_INVALID_ARG (null or misaligned pointer), BF_ERR_STATE
  * (weights never set), BF_ERR_HIP (launch failure).
@@ -189,8 +198,8 @@ int bf_plan_destroy(bf_plan_t plan);
  * uneven N, C, B, T; Sec. 1 mentions partitioning an array into independent
  * phased sub-arrays) run in one persistent launch: a grid sized to the
  * device whose workgroups take work units from a device queue spanning all
- * sets.  All plans must share precision and integration class (I == 1,
- * I == 2, or I >= 3) and have their weights set; up to 16 plans.  The batch
+ * sets.  All plans must share precision, input format and integration class
+ * (I == 1, I == 2, or I >= 3) and have their weights set; up to 16 plans.  The batch
  * references the plans (they must outlive it) and owns a device queue
  * counter.
  * Errors: BF_ERR_INVALID_ARG, BF_ERR_UNSUPPORTED, BF_ERR_OOM, BF_ERR_HIP.
@@ -220,20 +229,21 @@ int bf_batch_destroy(bf_batch_t batch);
  * same arguments: a hipGraph captured around one bf_table_run serves every
  * table stored afterwards.
  *
- * bf_table_create: for plans with n_antennas antennas, integration I and the
- * given precision (2 n_antennas must be a multiple of 16) on the current
- * device.  It fixes the launch: dynamic LDS of the largest batching variant
+ * bf_table_create: for plans with n_antennas antennas, integration I, the
+ * given precision and input format (flags: 0 or BF_INPUT_4BIT; 2 n_antennas
+ * must be a multiple of 16) on the current device.  It fixes the launch: dynamic LDS of the largest batching variant
  * that keeps two workgroups per CU, grid = CUs x workgroups per CU.  Owns a
  * device table (a few KB) and a queue counter.
  * Errors: BF_ERR_INVALID_ARG, BF_ERR_UNSUPPORTED, BF_ERR_OOM, BF_ERR_HIP.
  */
-int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, int32_t precision);
+int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, int32_t precision,
+                    uint32_t flags);
 
 /* Stores the set table for the next bf_table_run on `stream`: plans[i] with
  * voltages x_dev[i] and output p_dev[i] (device pointers, layout and
  * alignment as bf_run), 0 <= n <= 16; n = 0 makes the next run a no-op.
- * Every plan must match the table's antennas, integration, precision and
- * device and have its weights set; each set runs its own tile if the
+ * Every plan must match the table's antennas, integration, precision, input
+ * format and device and have its weights set; each set runs its own tile if the
  * batching kernel carries it and its LDS fits, else the closest that does.
  * The store is a one-workgroup kernel on `stream` (the table travels as its
  * argument), so the host arrays may be reused as soon as this returns; it is

@@ -13,6 +13,9 @@ The arithmetic lives in ``bf_oracle.c`` (plain FP64 loops, OpenMP over
   summed over non-overlapping windows of I samples.  ``x`` is int8
   [C][T][N][2] or complex128 [C][T][N] (unquantised input for the pins).
 * ``beams(w, x)``                -> complex128 [C][B][T] before detection.
+* ``unpack4(x4)``                -> int8 [...][2]: 4-bit complex samples (one
+  byte each, Sec. 2.1: two 4-bit two's complement components per antenna
+  sample) widened to (re, im); the real part is the high nibble.
 """
 from __future__ import annotations
 
@@ -135,3 +138,20 @@ def beams(w, x) -> np.ndarray:
     if lib().bfo_beams_f64(N, C, B, T, _p(wri), _p(xr), _p(out)) != 0:
         raise ValueError("bfo_beams_f64: invalid arguments")
     return out[..., 0] + 1j * out[..., 1]
+
+
+def unpack4(x4) -> np.ndarray:
+    """Decode packed 4-bit complex voltages: uint8 [...] -> int8 [...][2].
+
+    Each byte holds one antenna sample (Sec. 2.1): the real component in
+    bits 7..4 and the imaginary component in bits 3..0, each a 4-bit two's
+    complement number, so a nibble n >= 8 stands for n - 16 and the values
+    span [-8, 7]."""
+    b = np.asarray(x4)
+    if b.dtype != np.uint8:
+        raise ValueError("packed 4-bit voltages must be uint8")
+    hi = (b >> 4).astype(np.int16)
+    lo = (b & 0x0F).astype(np.int16)
+    re = np.where(hi >= 8, hi - 16, hi)
+    im = np.where(lo >= 8, lo - 16, lo)
+    return np.stack([re, im], axis=-1).astype(np.int8)

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbf.so")
 FP32, FP16, BF16 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "fp16": FP16, "bf16": BF16}
 ACCUMULATE = 1
+INPUT_4BIT = 2
 
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 
@@ -85,7 +86,7 @@ def lib() -> ctypes.CDLL:
         L.bf_batch_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(P), i32]
         L.bf_batch_run.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
         L.bf_batch_destroy.argtypes = [P]
-        L.bf_table_create.argtypes = [ctypes.POINTER(P), i32, i32, i32]
+        L.bf_table_create.argtypes = [ctypes.POINTER(P), i32, i32, i32, ctypes.c_uint32]
         L.bf_table_set.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), i32, P]
         L.bf_table_run.argtypes = [P, P]
         L.bf_table_destroy.argtypes = [P]
@@ -126,20 +127,37 @@ def _host_f64(a, shape) -> np.ndarray:
 
 class Plan:
     """One beam set: N antennas, C channels, B beams, T samples per block,
-    integration I.  Owns the device weights (see ``bf_plan_create_ex``)."""
+    integration I.  Owns the device weights (see ``bf_plan_create_ex``).
+    ``input_bits``: 8 (int8 [C][T][N][2]) or 4 (uint8 [C][T][N], real part in
+    the high nibble, imaginary part in the low nibble)."""
 
     def __init__(self, n_antennas: int, n_channels: int, n_beams: int, n_samples: int,
                  integration: int = 1, precision: str | int = "fp32",
-                 accumulate: bool = False):
+                 accumulate: bool = False, input_bits: int = 8):
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if input_bits not in (4, 8):
+            raise ValueError("input_bits must be 4 or 8")
+        flags = (ACCUMULATE if accumulate else 0) | (INPUT_4BIT if input_bits == 4 else 0)
         h = ctypes.c_void_p()
         _check(lib().bf_plan_create_ex(ctypes.byref(h), n_antennas, n_channels, n_beams,
-                                       n_samples, integration, prec,
-                                       ACCUMULATE if accumulate else 0), "bf_plan_create_ex")
+                                       n_samples, integration, prec, flags), "bf_plan_create_ex")
         self._h = h
         self.N, self.C, self.B, self.T, self.I = (n_antennas, n_channels, n_beams, n_samples,
                                                   integration)
         self.precision = prec
+        self.input_bits = input_bits
+
+    @property
+    def x_shape(self) -> tuple:
+        """Shape of one block of voltages for this plan's input format."""
+        if self.input_bits == 4:
+            return (self.C, self.T, self.N)
+        return (self.C, self.T, self.N, 2)
+
+    @property
+    def x_dtype(self):
+        import torch
+        return torch.uint8 if self.input_bits == 4 else torch.int8
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -174,8 +192,8 @@ class Plan:
 
     def check_io(self, x, p) -> None:
         import torch
-        if x.dtype != torch.int8 or tuple(x.shape) != (self.C, self.T, self.N, 2):
-            raise ValueError(f"x must be int8 [{self.C}][{self.T}][{self.N}][2], "
+        if x.dtype != self.x_dtype or tuple(x.shape) != self.x_shape:
+            raise ValueError(f"x must be {self.x_dtype} {list(self.x_shape)}, "
                              f"got {x.dtype} {tuple(x.shape)}")
         if p.dtype != torch.float32 or tuple(p.shape) != (self.C, self.B, self.windows):
             raise ValueError(f"p must be float32 [{self.C}][{self.B}][{self.windows}], "
@@ -185,7 +203,7 @@ class Plan:
                 raise ValueError("x and p must be contiguous device tensors")
 
     def run(self, x, p, stream=None) -> None:
-        """Enqueue one block: x int8 [C][T][N][2] -> p float32 [C][B][T/I]."""
+        """Enqueue one block: x (``x_shape``, ``x_dtype``) -> p float32 [C][B][T/I]."""
         self.check_io(x, p)
         _check(lib().bf_run(self.handle, x.data_ptr(), p.data_ptr(), _stream_ptr(stream)),
                "bf_run")
@@ -273,11 +291,13 @@ class Table:
     ``run`` enqueues the same two launches every time, so a graph captured
     around one ``run`` serves every later ``set``."""
 
-    def __init__(self, n_antennas: int, integration: int, precision="fp16"):
+    def __init__(self, n_antennas: int, integration: int, precision="fp16", input_bits: int = 8):
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if input_bits not in (4, 8):
+            raise ValueError("input_bits must be 4 or 8")
         h = ctypes.c_void_p()
-        _check(lib().bf_table_create(ctypes.byref(h), int(n_antennas), int(integration), prec),
-               "bf_table_create")
+        _check(lib().bf_table_create(ctypes.byref(h), int(n_antennas), int(integration), prec,
+                                     INPUT_4BIT if input_bits == 4 else 0), "bf_table_create")
         self._h = h
 
     def set(self, plans: Sequence[Plan], xs, ps, stream=None) -> None:

@@ -26,6 +26,7 @@ struct bf_plan_s {
   int32_t Bpad = 0, Kpad = 0;
   int mode = 0;
   bool vec16 = true;
+  bool in4 = false;  // 4-bit complex input (one byte per antenna sample)
   Tile tile{4, 1, 1};
   int32_t sgw = 1;
   int device = 0;
@@ -50,6 +51,7 @@ struct bf_batch_s {
 struct bf_table_s {
   int32_t N = 0, I = 0;
   int prec = 0, mode = 0;
+  bool in4 = false;
   int32_t Kpad = 0;
   size_t lds = 0;     // fixed dynamic LDS of every launch
   int grid = 1;       // fixed persistent grid: CUs x workgroups per CU
@@ -109,16 +111,31 @@ const Tile kGenTiles[] = {
     BF_TILE_LIST_GENERIC
 #undef BF_TILE
 };
+const Tile kIn4Tiles[] = {
+#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
+    BF_TILE_LIST_IN4
+#undef BF_TILE
+};
 
-bool tile_exists(bool vec16, Tile t) {
-  if (vec16) {
-    for (const Tile& x : kVecTiles)
-      if (x.mt == t.mt && x.nbt == t.nbt && x.nbp == t.nbp && x.kres == t.kres) return true;
-  } else {
-    for (const Tile& x : kGenTiles)
-      if (x.mt == t.mt && x.nbt == t.nbt && x.nbp == t.nbp && x.kres == t.kres) return true;
-  }
-  return false;
+bool same_tile(const Tile& a, const Tile& b) {
+  return a.mt == b.mt && a.nbt == b.nbt && a.nbp == b.nbp && a.kres == b.kres;
+}
+
+// The single-set variants compiled for a plan's input format and row width.
+template <class F>
+void for_each_tile(const bf_plan_s* p, F f) {
+  if (p->in4)
+    for (const Tile& x : kIn4Tiles) f(x);
+  else if (p->vec16)
+    for (const Tile& x : kVecTiles) f(x);
+  else
+    for (const Tile& x : kGenTiles) f(x);
+}
+
+bool tile_exists(const bf_plan_s* p, Tile t) {
+  bool found = false;
+  for_each_tile(p, [&](const Tile& x) { found = found || same_tile(x, t); });
+  return found;
 }
 
 // Work units per bf_run for a tile/sgw choice.
@@ -132,7 +149,7 @@ int64_t units_for(const bf_plan_s* p, Tile t, int32_t sgw) {
 
 // Whether a compiled tile can run plan p.
 bool tile_ok(const bf_plan_s* p, Tile t) {
-  if (!tile_exists(p->vec16, t)) return false;
+  if (!tile_exists(p, t)) return false;
   if (t.kres > 0 && p->Kpad / bf::kChunk > t.kres) return false;
   return lds_bytes(p->prec, p->Kpad, t.nbt) <= kLdsMax;
 }
@@ -152,12 +169,15 @@ void choose_tile(bf_plan_s* p) {
   if (!p->vec16) {
     t = nbt == 8 ? Tile{4, 8, 2, 0} : Tile{4, 1, 1, 0};
   } else if (nch == 1 && nbt >= 4) {
-    t = (p->prec == BF_FP32) ? Tile{4, nbt, 1, 1} : Tile{8, nbt, 1, 1};
+    t = (p->prec == BF_FP32 || p->in4) ? Tile{4, nbt, 1, 1} : Tile{8, nbt, 1, 1};
   } else if (nch == 2 && nbt >= 4) {
     t = Tile{4, nbt, 1, 2};
   } else {
     t = nbt >= 4 ? Tile{4, nbt, 2, 0} : nbt == 2 ? Tile{4, 2, 2, 0} : Tile{4, 1, 1, 0};
   }
+  // the 4-bit variants carry fewer register-resident forms: fall back to
+  // the streamed form of the same beam range
+  if (!tile_ok(p, t) && nbt >= 2) t = Tile{4, nbt, 2, 0};
   if (!tile_ok(p, t)) t = Tile{4, 1, 1, 0};
   int32_t G, QI, SG;
   schedule(p->I, p->T, &G, &QI, &SG);
@@ -323,7 +343,9 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
       return BF_ERR_INVALID_ARG;
     if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
       return BF_ERR_INVALID_ARG;
-    if (flags & ~BF_ACCUMULATE) return BF_ERR_INVALID_ARG;
+    if (flags & ~(BF_ACCUMULATE | BF_INPUT_4BIT)) return BF_ERR_INVALID_ARG;
+    // 4-bit rows are read 8 bytes (8 antennas) at a time
+    if ((flags & BF_INPUT_4BIT) && N % 8 != 0) return BF_ERR_UNSUPPORTED;
     bf_plan_s* p = new (std::nothrow) bf_plan_s();
     if (!p) return BF_ERR_OOM;
     p->N = N;
@@ -337,6 +359,7 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
     p->Kpad = (2 * N + bf::kChunk - 1) / bf::kChunk * bf::kChunk;
     p->mode = mode_of(I);
     p->vec16 = (2 * N) % 16 == 0;
+    p->in4 = (flags & BF_INPUT_4BIT) != 0;
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;
       return BF_ERR_HIP;
@@ -518,7 +541,7 @@ int bf_run(bf_plan_t p, const int8_t* x, float* out, void* stream) {
     L.xcd_remap = 1;
     const int64_t grid = (L.total_units + 7) / 8 * 8;
     if (grid > 0x7FFFFFFF) return BF_ERR_UNSUPPORTED;
-    hipError_t e = bf::launch_beamform(p->prec, p->mode, p->vec16, p->tile, L, (int)grid,
+    hipError_t e = bf::launch_beamform(p->prec, p->mode, p->vec16, p->in4, p->tile, L, (int)grid,
                                        lds_bytes(p->prec, p->Kpad, p->tile.nbt),
                                        reinterpret_cast<hipStream_t>(stream));
     return from_hip(e);
@@ -576,10 +599,7 @@ int bf_plan_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
     }
     ++n;
   };
-  if (p->vec16)
-    for (const Tile& t : kVecTiles) add(t);
-  else
-    for (const Tile& t : kGenTiles) add(t);
+  for_each_tile(p, add);
   return n;
 }
 
@@ -612,7 +632,7 @@ int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n) {
       const bf_plan_s* a = plans[0];
       const bf_plan_s* b = plans[i];
       if (b->prec != a->prec || b->mode != a->mode || b->vec16 != a->vec16 ||
-          b->device != a->device)
+          b->in4 != a->in4 || b->device != a->device)
         return BF_ERR_UNSUPPORTED;
     }
     bf_batch_s* bt = new bf_batch_s();
@@ -647,7 +667,7 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
     hipError_t e = hipSuccess;
     if (multi) {
       int occ = 0;
-      e = bf::launch_beamform_multi(p0->prec, p0->mode, L, nullptr, 0, lds, s, &occ);
+      e = bf::launch_beamform_multi(p0->prec, p0->mode, p0->in4, L, nullptr, 0, lds, s, &occ);
       if (e != hipSuccess) return from_hip(e);
       per_cu = std::max(1, occ);
     }
@@ -655,9 +675,10 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
     if (grid < 1) grid = 1;
     e = bf::launch_queue_reset(bt->queue, s);
     if (e == hipSuccess) {
-      e = multi ? bf::launch_beamform_multi(p0->prec, p0->mode, L, nullptr, (int)grid, lds, s,
-                                            nullptr)
-                : bf::launch_beamform(p0->prec, p0->mode, p0->vec16, common, L, (int)grid, lds, s);
+      e = multi ? bf::launch_beamform_multi(p0->prec, p0->mode, p0->in4, L, nullptr, (int)grid,
+                                            lds, s, nullptr)
+                : bf::launch_beamform(p0->prec, p0->mode, p0->vec16, p0->in4, common, L,
+                                      (int)grid, lds, s);
     }
     return from_hip(e);
   } catch (...) {
@@ -673,18 +694,21 @@ int bf_batch_destroy(bf_batch_t bt) {
   return BF_OK;
 }
 
-int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, int32_t precision) {
+int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, int32_t precision,
+                    uint32_t flags) {
   try {
     if (!out) return BF_ERR_INVALID_ARG;
     *out = nullptr;
     if (n_antennas < 1 || n_antennas > kMaxN || integration < 1) return BF_ERR_INVALID_ARG;
     if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
       return BF_ERR_INVALID_ARG;
+    if (flags & ~BF_INPUT_4BIT) return BF_ERR_INVALID_ARG;
     if ((2 * n_antennas) % 16 != 0) return BF_ERR_UNSUPPORTED;
     bf_table_s* t = new bf_table_s();
     t->N = n_antennas;
     t->I = integration;
     t->prec = precision;
+    t->in4 = (flags & BF_INPUT_4BIT) != 0;
     t->mode = mode_of(integration);
     t->Kpad = 64 * ((2 * n_antennas + 63) / 64);
     // one LDS size for every launch: the largest batching variant that still
@@ -707,7 +731,8 @@ int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, in
     if (e == hipSuccess) {
       Launch L;
       std::memset(&L, 0, sizeof(L));
-      e = bf::launch_beamform_multi(precision, t->mode, L, t->table, 0, t->lds, nullptr, &occ);
+      e = bf::launch_beamform_multi(precision, t->mode, t->in4, L, t->table, 0, t->lds, nullptr,
+                                    &occ);
     }
     if (e != hipSuccess) {
       if (t->queue) (void)hipFree(t->queue);
@@ -731,7 +756,8 @@ int bf_table_set(bf_table_t t, const bf_plan_t* plans, const int8_t* const* x, f
     for (int i = 0; i < n; ++i) {
       const bf_plan_s* p = plans[i];
       if (!p) return BF_ERR_INVALID_ARG;
-      if (p->N != t->N || p->I != t->I || p->prec != t->prec || p->device != t->device)
+      if (p->N != t->N || p->I != t->I || p->prec != t->prec || p->in4 != t->in4 ||
+          p->device != t->device)
         return BF_ERR_UNSUPPORTED;
     }
     Launch L;
@@ -756,7 +782,8 @@ int bf_table_run(bf_table_t t, void* stream) {
   std::memset(&unused, 0, sizeof(unused));
   hipError_t e = bf::launch_queue_reset(t->queue, s);
   if (e == hipSuccess)
-    e = bf::launch_beamform_multi(t->prec, t->mode, unused, t->table, t->grid, t->lds, s, nullptr);
+    e = bf::launch_beamform_multi(t->prec, t->mode, t->in4, unused, t->table, t->grid, t->lds, s,
+                                  nullptr);
   return from_hip(e);
 }
 
@@ -773,35 +800,48 @@ int bf_table_destroy(bf_table_t t) {
 
 namespace bf {
 
-template <int PREC>
-hipError_t launch_prec(int mode, bool vec16, Tile t, const Launch& L, int grid, size_t lds,
-                       hipStream_t s);
-extern template hipError_t launch_prec<0>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
-extern template hipError_t launch_prec<1>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
-extern template hipError_t launch_prec<2>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
+template <int PREC, bool IN4>
+hipError_t launch_prec_in(int mode, bool vec16, Tile t, const Launch& L, int grid, size_t lds,
+                          hipStream_t s);
+template <int PREC, bool IN4>
+hipError_t launch_multi_in(int mode, const Launch& L, const Launch* table, int grid, size_t lds,
+                           hipStream_t s, int* occupancy);
+#define BF_EXTERN(P, F)                                                                     \
+  extern template hipError_t launch_prec_in<P, F>(int, bool, Tile, const Launch&, int, size_t, \
+                                                  hipStream_t);                              \
+  extern template hipError_t launch_multi_in<P, F>(int, const Launch&, const Launch*, int,    \
+                                                   size_t, hipStream_t, int*);
+BF_EXTERN(0, false)
+BF_EXTERN(1, false)
+BF_EXTERN(2, false)
+BF_EXTERN(0, true)
+BF_EXTERN(1, true)
+BF_EXTERN(2, true)
+#undef BF_EXTERN
 
-template <int PREC>
-hipError_t launch_multi_prec(int mode, const Launch& L, const Launch* table, int grid, size_t lds,
-                             hipStream_t s, int* occupancy);
-extern template hipError_t launch_multi_prec<0>(int, const Launch&, const Launch*, int, size_t,
-                                                hipStream_t, int*);
-extern template hipError_t launch_multi_prec<1>(int, const Launch&, const Launch*, int, size_t,
-                                                hipStream_t, int*);
-extern template hipError_t launch_multi_prec<2>(int, const Launch&, const Launch*, int, size_t,
-                                                hipStream_t, int*);
-
-hipError_t launch_beamform_multi(int prec, int mode, const Launch& L, const Launch* table,
-                                 int grid, size_t lds_bytes, hipStream_t stream, int* occupancy) {
-  if (prec == 0) return launch_multi_prec<0>(mode, L, table, grid, lds_bytes, stream, occupancy);
-  if (prec == 1) return launch_multi_prec<1>(mode, L, table, grid, lds_bytes, stream, occupancy);
-  return launch_multi_prec<2>(mode, L, table, grid, lds_bytes, stream, occupancy);
+hipError_t launch_beamform_multi(int prec, int mode, bool in4, const Launch& L,
+                                 const Launch* table, int grid, size_t lds, hipStream_t s,
+                                 int* occ) {
+  if (in4) {
+    if (prec == 0) return launch_multi_in<0, true>(mode, L, table, grid, lds, s, occ);
+    if (prec == 1) return launch_multi_in<1, true>(mode, L, table, grid, lds, s, occ);
+    return launch_multi_in<2, true>(mode, L, table, grid, lds, s, occ);
+  }
+  if (prec == 0) return launch_multi_in<0, false>(mode, L, table, grid, lds, s, occ);
+  if (prec == 1) return launch_multi_in<1, false>(mode, L, table, grid, lds, s, occ);
+  return launch_multi_in<2, false>(mode, L, table, grid, lds, s, occ);
 }
 
-hipError_t launch_beamform(int prec, int mode, bool vec16, Tile tile, const Launch& L, int grid,
-                           size_t lds_bytes, hipStream_t stream) {
-  if (prec == 0) return launch_prec<0>(mode, vec16, tile, L, grid, lds_bytes, stream);
-  if (prec == 1) return launch_prec<1>(mode, vec16, tile, L, grid, lds_bytes, stream);
-  return launch_prec<2>(mode, vec16, tile, L, grid, lds_bytes, stream);
+hipError_t launch_beamform(int prec, int mode, bool vec16, bool in4, Tile tile, const Launch& L,
+                           int grid, size_t lds, hipStream_t s) {
+  if (in4) {
+    if (prec == 0) return launch_prec_in<0, true>(mode, vec16, tile, L, grid, lds, s);
+    if (prec == 1) return launch_prec_in<1, true>(mode, vec16, tile, L, grid, lds, s);
+    return launch_prec_in<2, true>(mode, vec16, tile, L, grid, lds, s);
+  }
+  if (prec == 0) return launch_prec_in<0, false>(mode, vec16, tile, L, grid, lds, s);
+  if (prec == 1) return launch_prec_in<1, false>(mode, vec16, tile, L, grid, lds, s);
+  return launch_prec_in<2, false>(mode, vec16, tile, L, grid, lds, s);
 }
 
 }  // namespace bf

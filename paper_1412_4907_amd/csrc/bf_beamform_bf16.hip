@@ -1,9 +1,10 @@
-// Beamform kernel instantiations for one storage precision (bf16).
+// Beamform kernel instantiations for one storage precision and input format (bf16, int8 input).
 #include "bf_internal.h"
 #include "bf_beamform.inc"
 
 namespace bf {
-template hipError_t launch_prec<2>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
-template hipError_t launch_multi_prec<2>(int, const Launch&, const Launch*, int, size_t,
-                                            hipStream_t, int*);
+template hipError_t launch_prec_in<2, false>(int, bool, Tile, const Launch&, int, size_t,
+                                             hipStream_t);
+template hipError_t launch_multi_in<2, false>(int, const Launch&, const Launch*, int, size_t,
+                                              hipStream_t, int*);
 }

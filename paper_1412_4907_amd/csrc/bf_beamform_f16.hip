@@ -1,9 +1,10 @@
-// Beamform kernel instantiations for one storage precision (f16).
+// Beamform kernel instantiations for one storage precision and input format (f16, int8 input).
 #include "bf_internal.h"
 #include "bf_beamform.inc"
 
 namespace bf {
-template hipError_t launch_prec<1>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
-template hipError_t launch_multi_prec<1>(int, const Launch&, const Launch*, int, size_t,
-                                            hipStream_t, int*);
+template hipError_t launch_prec_in<1, false>(int, bool, Tile, const Launch&, int, size_t,
+                                             hipStream_t);
+template hipError_t launch_multi_in<1, false>(int, const Launch&, const Launch*, int, size_t,
+                                              hipStream_t, int*);
 }

@@ -1,9 +1,10 @@
-// Beamform kernel instantiations for one storage precision (f32).
+// Beamform kernel instantiations for one storage precision and input format (f32, int8 input).
 #include "bf_internal.h"
 #include "bf_beamform.inc"
 
 namespace bf {
-template hipError_t launch_prec<0>(int, bool, Tile, const Launch&, int, size_t, hipStream_t);
-template hipError_t launch_multi_prec<0>(int, const Launch&, const Launch*, int, size_t,
-                                            hipStream_t, int*);
+template hipError_t launch_prec_in<0, false>(int, bool, Tile, const Launch&, int, size_t,
+                                             hipStream_t);
+template hipError_t launch_multi_in<0, false>(int, const Launch&, const Launch*, int, size_t,
+                                              hipStream_t, int*);
 }

@@ -66,6 +66,10 @@ struct Tile {
   BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 1, 2) BF_TILE(4, 8, 2, 0)  \
   BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 2, 1, 0) BF_TILE(4, 1, 1, 0)
 #define BF_TILE_LIST_GENERIC BF_TILE(4, 8, 2, 0) BF_TILE(4, 1, 1, 0)
+// Variants compiled for 4-bit input.
+#define BF_TILE_LIST_IN4                                                          \
+  BF_TILE(4, 8, 1, 1) BF_TILE(4, 8, 2, 1) BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2)  \
+  BF_TILE(4, 8, 2, 0) BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 1, 1, 0)
 // Variants compiled into the persistent batching kernel (16-byte loads).
 // (MT = 8 variants are left out: their register use would halve the
 // kernel's occupancy for every set.)
@@ -73,15 +77,16 @@ struct Tile {
   BF_TILE(4, 8, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0)  \
   BF_TILE(4, 1, 1, 0)
 
-// Host-side launcher for one (precision, mode, vec16, tile) instantiation.
-// Returns hipSuccess or the launch error.
-hipError_t launch_beamform(int prec, int mode, bool vec16, Tile tile, const Launch& L,
+// Host-side launcher for one (precision, mode, vec16, input format, tile)
+// instantiation.  Returns hipSuccess or the launch error.
+hipError_t launch_beamform(int prec, int mode, bool vec16, bool in4, Tile tile, const Launch& L,
                            int grid, size_t lds_bytes, hipStream_t stream);
 // Persistent batching kernel (per-set variants).  table != null: the form
 // that reads its set table from that device copy (L unused).
 // occupancy != null only queries workgroups per CU.
-hipError_t launch_beamform_multi(int prec, int mode, const Launch& L, const Launch* table,
-                                 int grid, size_t lds_bytes, hipStream_t stream, int* occupancy);
+hipError_t launch_beamform_multi(int prec, int mode, bool in4, const Launch& L,
+                                 const Launch* table, int grid, size_t lds_bytes,
+                                 hipStream_t stream, int* occupancy);
 
 hipError_t launch_weights_geom(int prec, const double* pos, const double* dir,
                                const double* freq, int N, int C, int B, int Bpad, int Kpad,

@@ -2,7 +2,10 @@
 
 This module is shared by the GPU path's tests/bench and by the CPU oracle's
 tests.  It holds no beamforming arithmetic: it only draws antenna layouts,
-beam pointings, channel frequencies and int8 complex voltages.  A point
+beam pointings, channel frequencies and int8 complex voltages, or 4-bit
+complex voltages packed one antenna sample per byte (Sec. 2.1: the BEST-2
+F-engine emits 4-bit two's complement components), real part in the high
+nibble.  A point
 source is injected as a plane wave arriving at antenna n with the geometric
 phase exp(+i 2 pi f (k_s . r_n) / c0) (Sec. 1, the delay/phase picture that
 Eq. 1 builds on); that is the input model, not the beam sum.
@@ -38,6 +41,7 @@ import numpy as np
 C0 = 299_792_458.0  # speed of light in vacuum, m/s (exact SI value)
 SEED = 4907
 SIGMA = 16.0
+SIGMA4 = 2.0  # noise level of 4-bit workloads: 4 sigma reaches the [-8, 7] rails
 
 # workload ids used as the first spawn-key element
 CFG_IDS = {"small": 1, "paper": 2, "precision": 3, "batch": 4, "serve": 5}
@@ -127,11 +131,31 @@ def quantise(v: np.ndarray) -> np.ndarray:
     return v.astype(np.int8)
 
 
+def quantise4(v: np.ndarray) -> np.ndarray:
+    """Round half to even, clip to the 4-bit two's complement range [-8, 7],
+    cast to int8."""
+    v = np.rint(v, out=v) if v.dtype.kind == "f" else np.rint(v)
+    np.clip(v, -8, 7, out=v)
+    return v.astype(np.int8)
+
+
+def pack4(x: np.ndarray) -> np.ndarray:
+    """int8 [...][2] with components in [-8, 7] -> uint8 [...], one byte per
+    sample: real part in the high nibble, imaginary part in the low nibble,
+    each as 4-bit two's complement."""
+    x = np.asarray(x)
+    if x.shape[-1] != 2 or x.min(initial=0) < -8 or x.max(initial=0) > 7:
+        raise ValueError("pack4 takes [...][2] components in [-8, 7]")
+    u = x.astype(np.uint8) & np.uint8(0x0F)
+    return (u[..., 0] << np.uint8(4)) | u[..., 1]
+
+
 def channel_voltages(cfg: int | str, chan: int, n_samples: int, pos: np.ndarray,
                      freq_hz: float, sources: Sequence[Source] = (),
-                     sigma: float = SIGMA, t0: int = 0) -> np.ndarray:
+                     sigma: float = SIGMA, t0: int = 0, bits: int = 8) -> np.ndarray:
     """int8 [T][N][2] voltages for one channel (re, im interleaved,
-    antenna-fastest).  Noise is N(0, sigma^2) per component, drawn as float32
+    antenna-fastest), or for ``bits`` = 4 uint8 [T][N] packed samples
+    (``pack4``).  Noise is N(0, sigma^2) per component, drawn as float32
     from the (cfg, chan) stream; each source adds amp * envelope(t) *
     exp(+2 pi i f (k_s . r_n) / c0), phases taken in float64 and the product
     formed in complex64.  ``t0`` offsets tone phases only."""
@@ -150,6 +174,8 @@ def channel_voltages(cfg: int | str, chan: int, n_samples: int, pos: np.ndarray,
             src = env.astype(np.complex64)[:, None] * ph.astype(np.complex64)[None, :]
             v[..., 0] += src.real
             v[..., 1] += src.imag
+    if bits == 4:
+        return pack4(quantise4(v))
     return quantise(v)
 
 
@@ -171,25 +197,37 @@ class Workload:
     freqs: np.ndarray          # [C] Hz
     sources: list = field(default_factory=list)
     sigma: float = SIGMA
+    input_bits: int = 8        # 8: int8 [C][T][N][2]; 4: packed uint8 [C][T][N]
 
     @property
     def flops(self) -> float:
         """8 flop per complex multiply-accumulate (Sec. 2.2)."""
         return 8.0 * self.n_chan * self.n_beams * self.n_samples * self.n_ant
 
+    def x_shape(self, n_chan: int, n_samples: int) -> tuple:
+        if self.input_bits == 4:
+            return (n_chan, n_samples, self.n_ant)
+        return (n_chan, n_samples, self.n_ant, 2)
+
+    @property
+    def x_dtype(self):
+        return np.uint8 if self.input_bits == 4 else np.int8
+
     def channel(self, c: int, n_samples: Optional[int] = None, t0: int = 0) -> np.ndarray:
         return channel_voltages(self.cfg, c, n_samples or self.n_samples, self.pos,
-                                float(self.freqs[c]), self.sources, self.sigma, t0)
+                                float(self.freqs[c]), self.sources, self.sigma, t0,
+                                self.input_bits)
 
     def voltages(self, channels: Optional[Sequence[int]] = None,
                  n_samples: Optional[int] = None, out: Optional[np.ndarray] = None,
                  workers: int = 1) -> np.ndarray:
-        """int8 [len(channels)][T][N][2].  ``workers`` > 1 fills channels in a
-        thread pool (numpy releases the GIL in the heavy calls)."""
+        """int8 [len(channels)][T][N][2] (packed uint8 [len(channels)][T][N]
+        for a 4-bit workload).  ``workers`` > 1 fills channels in a thread
+        pool (numpy releases the GIL in the heavy calls)."""
         chans = list(range(self.n_chan)) if channels is None else list(channels)
         T = n_samples or self.n_samples
         if out is None:
-            out = np.empty((len(chans), T, self.n_ant, 2), dtype=np.int8)
+            out = np.empty(self.x_shape(len(chans), T), dtype=self.x_dtype)
         if workers <= 1:
             for i, c in enumerate(chans):
                 out[i] = self.channel(c, T)
@@ -248,6 +286,17 @@ def paper() -> Workload:
     src = [Source(dirs[b].copy(), 16.0, "noise") for b in beams]
     return Workload("paper", CFG_IDS["paper"], N, C, B, T, 16, pos, dirs,
                     channel_freqs(C, 400e6, 16e6), src)
+
+
+def four_bit(w: Workload) -> Workload:
+    """The same workload with 4-bit packed input (the BEST-2 format): noise and
+    sources scaled by SIGMA4 / SIGMA, so the signal-to-noise ratio is kept
+    and the draws come from the same streams."""
+    import dataclasses
+    k = SIGMA4 / w.sigma
+    src = [dataclasses.replace(s, amp=s.amp * k) for s in w.sources]
+    return dataclasses.replace(w, name=w.name + "_4bit", sources=src, sigma=SIGMA4,
+                               input_bits=4)
 
 
 def random_dirs(n: int, g: np.random.Generator, max_deg: float = 30.0) -> np.ndarray:

@@ -47,6 +47,9 @@ def test_validation_before_any_device_call():
     assert L.bf_plan_create_ex(ctypes.byref(h), 4, 1, 1, 10, 3, 0, 0) == bf.ERR_INVALID_ARG
     assert L.bf_plan_create_ex(ctypes.byref(h), 4, 1, 1, 16, 1, 7, 0) == bf.ERR_INVALID_ARG
     assert L.bf_plan_create_ex(ctypes.byref(h), 4, 1, 1, 16, 1, 0, 8) == bf.ERR_INVALID_ARG
+    # 4-bit rows are read 8 antennas at a time
+    assert L.bf_plan_create_ex(ctypes.byref(h), 12, 1, 1, 16, 1, 0, bf.INPUT_4BIT) == \
+        bf.ERR_UNSUPPORTED
     assert L.bf_plan_create_ex(None, 4, 1, 1, 16, 1, 0, 0) == bf.ERR_INVALID_ARG
     assert L.bf_run(None, None, None, None) == bf.ERR_INVALID_ARG
     assert L.bf_set_weights(None, None, None, None, None) == bf.ERR_INVALID_ARG
@@ -55,11 +58,12 @@ def test_validation_before_any_device_call():
     assert L.bf_batch_destroy(None) == bf.OK
     assert L.bf_batch_create(None, None, 1) == bf.ERR_INVALID_ARG
     # table batch: sizes, precision and 16-byte rows are checked first
-    assert L.bf_table_create(None, 32, 16, 1) == bf.ERR_INVALID_ARG
-    assert L.bf_table_create(ctypes.byref(h), 0, 16, 1) == bf.ERR_INVALID_ARG
-    assert L.bf_table_create(ctypes.byref(h), 32, 0, 1) == bf.ERR_INVALID_ARG
-    assert L.bf_table_create(ctypes.byref(h), 32, 16, 5) == bf.ERR_INVALID_ARG
-    assert L.bf_table_create(ctypes.byref(h), 33, 16, 1) == bf.ERR_UNSUPPORTED
+    assert L.bf_table_create(None, 32, 16, 1, 0) == bf.ERR_INVALID_ARG
+    assert L.bf_table_create(ctypes.byref(h), 0, 16, 1, 0) == bf.ERR_INVALID_ARG
+    assert L.bf_table_create(ctypes.byref(h), 32, 0, 1, 0) == bf.ERR_INVALID_ARG
+    assert L.bf_table_create(ctypes.byref(h), 32, 16, 5, 0) == bf.ERR_INVALID_ARG
+    assert L.bf_table_create(ctypes.byref(h), 32, 16, 1, bf.ACCUMULATE) == bf.ERR_INVALID_ARG
+    assert L.bf_table_create(ctypes.byref(h), 33, 16, 1, 0) == bf.ERR_UNSUPPORTED
     assert L.bf_table_set(None, None, None, None, 0, None) == bf.ERR_INVALID_ARG
     assert L.bf_table_run(None, None) == bf.ERR_INVALID_ARG
     assert L.bf_table_destroy(None) == bf.OK

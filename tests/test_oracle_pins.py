@@ -7,7 +7,9 @@ conjugated weights, transposed operand, dropped imaginary cross term, wrong
 window indexing) fails at least one of them; ``test_planted_mistakes``
 checks that claim by planting such slips in a Python twin of the oracle.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -264,3 +266,38 @@ def test_rejects_bad_args():
         oracle.beamform(W, np.zeros((1, 10, 2, 2), np.int8), 3)
     with pytest.raises(ValueError):
         oracle.beamform(W, np.zeros((1, 10, 3, 2), np.int8), 1)
+
+
+# --- 4-bit packed input (Sec. 2.1: 4-bit two's complement components) -------
+
+NIBBLES = os.path.join(os.path.dirname(__file__), "golden", "nibbles.json")
+
+
+def test_unpack4_worked_bytes():
+    rows = json.load(open(NIBBLES))["samples"]
+    b = np.array([r[0] for r in rows], dtype=np.uint8)
+    got = oracle.unpack4(b)
+    assert got.dtype == np.int8
+    assert got.tolist() == [[r[1], r[2]] for r in rows]
+
+
+def test_unpack4_covers_the_grid_once():
+    """All 256 bytes decode to 256 distinct pairs, i.e. every point of
+    [-8, 7] x [-8, 7] exactly once, and the generator's packing inverts it."""
+    x = oracle.unpack4(np.arange(256, dtype=np.uint8).reshape(16, 16))
+    pairs = {tuple(v) for v in x.reshape(-1, 2).tolist()}
+    assert len(pairs) == 256
+    assert pairs == {(a, b) for a in range(-8, 8) for b in range(-8, 8)}
+    assert np.array_equal(synth.pack4(x), np.arange(256, dtype=np.uint8).reshape(16, 16))
+
+
+def test_4bit_block_closed_forms():
+    """Unit weights: a block of identical samples v sums to N v per beam, so
+    the power over I samples is I N^2 |v|^2 (Sec. 2.1), for a real, an
+    imaginary and a rail value."""
+    N, T, I = 8, 32, 4
+    W = np.ones((1, 1, N), dtype=complex)
+    for byte, v in [(0x70, 7), (0x0F, -1j), (0x88, -8 - 8j), (0x3D, 3 - 3j)]:
+        x4 = np.full((1, T, N), byte, dtype=np.uint8)
+        P = oracle.beamform(W, oracle.unpack4(x4), I)
+        np.testing.assert_array_equal(P, I * N * N * (np.real(v) ** 2 + np.imag(v) ** 2))

@@ -61,3 +61,22 @@ def test_paper_accounting_numbers():
     assert abs(rate / 1e9 - d["gbps"]) < 1e-12
     # the serving block: 8192 samples at 16 MHz / 1024 channels
     assert abs(8192 / synth.SERVE_CHAN_RATE - 0.524288) < 1e-12
+
+
+def test_four_bit_workload():
+    w = synth.four_bit(synth.paper())
+    x = w.voltages(channels=[0, 3], n_samples=2048)
+    assert x.dtype == np.uint8 and x.shape == (2, 2048, 32)
+    assert w.input_bits == 4 and w.sigma == synth.SIGMA4
+    # real and imaginary nibbles as 4-bit two's complement, decoded here by
+    # sign-extending shifts rather than the oracle's reading
+    s = x.view(np.int8)
+    re = (s >> 4).astype(float)
+    im = ((s << 4).astype(np.int8) >> 4).astype(float)
+    assert re.min() >= -8 and re.max() <= 7 and im.min() >= -8 and im.max() <= 7
+    # sigma=2 noise plus three noise-like sources of amplitude 2: variance
+    # 4 + 3 * 2 = 10 per component, less a little clipping at the rails
+    assert 9.0 < re.var() < 10.6 and 9.0 < im.var() < 10.6
+    assert np.array_equal(x[1], w.voltages(channels=[3], n_samples=2048)[0])
+    v = np.array([0.5, 1.5, -0.5, -8.5, 7.5, -20.0, 20.0])
+    assert synth.quantise4(v.copy()).tolist() == [0, 2, 0, -8, 7, -8, 7]
