@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--input-bits", type=int, default=8, choices=[8, 4],
+                    help="voltage format: int8 pairs, or 4-bit pairs packed one per byte")
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "small", "precision", "serve", "batch"])
     ap.add_argument("--blocks", type=int, default=200, help="serve: blocks to stream")
@@ -106,7 +108,7 @@ def algorithmic_bytes(w, prec) -> float:
     """Bytes one launch must move at minimum: every voltage once, every
     weight once, every output window once."""
     es = 4 if prec == "fp32" else 2
-    x = w.n_chan * w.n_samples * w.n_ant * 2
+    x = w.n_chan * w.n_samples * w.n_ant * (1 if w.input_bits == 4 else 2)
     wt = w.n_chan * w.n_beams * w.n_ant * 2 * es
     p = w.n_chan * w.n_beams * (w.n_samples // w.integration) * 4
     return float(x + wt + p)
@@ -144,21 +146,23 @@ def cpu_baseline(w, budget_s: float) -> dict:
     order = g.permutation(w.n_chan)
     W = oracle.weights(w.pos, w.dirs, w.freqs[order[:1]])
     x1 = w.voltages(channels=order[:1])
+    four = w.input_bits == 4
     t = time.perf_counter()
-    oracle.beamform(W, x1, w.integration)
+    oracle.beamform(W, oracle.unpack4(x1) if four else x1, w.integration)
     t1 = time.perf_counter() - t
     n = int(max(1, min(w.n_chan - 1, budget_s / max(t1, 1e-3))))
     chans = order[1:1 + n]
     W = oracle.weights(w.pos, w.dirs, w.freqs[chans])
     x = w.voltages(channels=chans, workers=8)
     t = time.perf_counter()
-    oracle.beamform(W, x, w.integration)
+    oracle.beamform(W, oracle.unpack4(x) if four else x, w.integration)
     dt = time.perf_counter() - t
     flops = 8.0 * len(chans) * w.n_beams * w.n_samples * w.n_ant
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.max_threads(),
             "kind": "oracle",
             "sample": f"{len(chans)} of {w.n_chan} channels (seeded), all {w.n_beams} beams x "
-                      f"{w.n_samples} samples x {w.n_ant} antennas, I={w.integration}; "
+                      f"{w.n_samples} samples x {w.n_ant} antennas, I={w.integration}"
+                      f"{', 4-bit input decoded in the timed region' if four else ''}; "
                       f"{dt:.1f} s FP64 on the host"}
 
 
@@ -397,6 +401,9 @@ def main():
     if a.workload == "batch":
         return batch_bench(a, torch, dev)
     w = workload(a.workload)
+    if a.input_bits == 4:
+        from paper_1412_4907_amd import synth
+        w = synth.four_bit(w)
     t0 = time.perf_counter()
     x = w.voltages(workers=16)
     gen_s = time.perf_counter() - t0
@@ -405,7 +412,8 @@ def main():
     windows = w.n_samples // w.integration
 
     def leg(prec, steps, warmup):
-        plan = bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration, precision=prec)
+        plan = bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration, precision=prec,
+                       input_bits=w.input_bits)
         plan.set_weights(w.pos, w.dirs, w.freqs)
         p = torch.empty((w.n_chan, w.n_beams, windows), dtype=torch.float32, device=dev)
         # tile shape from the autotuner's cache, else tuned now (untimed)
@@ -454,7 +462,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: N={w.n_ant} antennas, C={w.n_chan} channels, "
                                f"B={w.n_beams} beams, T={w.n_samples} samples, I={w.integration}",
-                   "precision": a.precision, "n_antennas": w.n_ant, "n_channels": w.n_chan,
+                   "precision": a.precision, "input_bits": w.input_bits,
+                   "n_antennas": w.n_ant, "n_channels": w.n_chan,
                    "n_beams": w.n_beams, "n_samples": w.n_samples, "integration": w.integration,
                    "tile": {"mt": info["tile_mt"], "nbt": info["tile_nbt"],
                             "nbp": info["tile_nbp"], "kres": info["tile_kres"],
