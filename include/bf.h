@@ -80,6 +80,17 @@ enum {
  * The result equals, bit for bit, the int8 form run on the same values
  * widened to [C][T][N][2].  Half the input bytes of the int8 form. */
 #define BF_INPUT_4BIT 2u
+/* Complex (electric-field) beam output instead of detected power (Sec. 1.1:
+ * the S-engine emits selected beams as 16-bit complex words for coherent
+ * downstream processing such as pulsar folding).  P is then device
+ * [C][B][T] complex samples, each two IEEE binary16 values (re, im) in
+ * 4 bytes, beam-major so each beam's series is contiguous: the value
+ * written is s * B[c][b][t] per component (s = bf_plan_set_output_scale,
+ * default 1), clamped to +-65504 and rounded to nearest even once from the
+ * FP32 accumulation.  Requires integration 1 and excludes BF_ACCUMULATE
+ * (else BF_ERR_INVALID_ARG); not accepted by the batching and table forms
+ * (BF_ERR_UNSUPPORTED). */
+#define BF_OUTPUT_COMPLEX 4u
 
 /* Human-readable text for a status code (static storage, never NULL). */
 const char* bf_strerror(int status);
@@ -141,8 +152,9 @@ int bf_get_weights(bf_plan_t plan, double* weights_out, void* stream);
 
 /*
  * The hot path: one block.  x_dev: device int8 [C][T][N][2] (uint8 [C][T][N]
- * for a BF_INPUT_4BIT plan); p_dev: device float [C][B][T/I]; both 16-byte
- * aligned and not overlapping.  Enqueues
+ * for a BF_INPUT_4BIT plan); p_dev: device float [C][B][T/I] (FP16 pairs
+ * [C][B][T][2] for a BF_OUTPUT_COMPLEX plan); both 16-byte aligned and not
+ * overlapping.  Enqueues
  * one kernel on `stream`; no host synchronisation, no allocation.
  * Errors: BF_ERR_INVALID_ARG (null or misaligned pointer), BF_ERR_STATE
  * (weights never set), BF_ERR_HIP (launch failure).
@@ -180,6 +192,15 @@ int bf_plan_info(bf_plan_t plan, bf_plan_info_t* info);
  */
 int bf_plan_set_tile(bf_plan_t plan, int32_t mt, int32_t nbt, int32_t nbp, int32_t kres,
                      int32_t sg_per_wave);
+
+/*
+ * Scale applied to the complex beams of a BF_OUTPUT_COMPLEX plan before
+ * their FP16 rounding (so that |s B| stays within the FP16 range, e.g.
+ * 1/sqrt(N) for noise-like inputs).  Takes effect for later bf_run calls.
+ * Errors: BF_ERR_INVALID_ARG (null plan, scale not finite or <= 0),
+ * BF_ERR_STATE (the plan does not output complex beams).
+ */
+int bf_plan_set_output_scale(bf_plan_t plan, float scale);
 
 /*
  * List the compiled tile variants that can run this plan: writes up to

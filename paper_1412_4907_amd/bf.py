@@ -20,13 +20,15 @@ FP32, FP16, BF16 = 0, 1, 2
 PRECISIONS = {"fp32": FP32, "fp16": FP16, "bf16": BF16}
 ACCUMULATE = 1
 INPUT_4BIT = 2
+OUTPUT_COMPLEX = 4
 
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 
 # every entry point declared in include/bf.h
 EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_plan_create",
            "bf_plan_create_ex", "bf_set_weights", "bf_set_weights_raw", "bf_get_weights",
-           "bf_run", "bf_plan_info", "bf_plan_set_tile", "bf_plan_tile_candidates",
+           "bf_run", "bf_plan_info", "bf_plan_set_tile", "bf_plan_set_output_scale",
+           "bf_plan_tile_candidates",
            "bf_plan_destroy", "bf_batch_create", "bf_batch_tile_candidates", "bf_batch_run",
            "bf_batch_destroy", "bf_table_create", "bf_table_set", "bf_table_run",
            "bf_table_destroy"]
@@ -80,6 +82,7 @@ def lib() -> ctypes.CDLL:
         L.bf_run.argtypes = [P, P, P, P]
         L.bf_plan_info.argtypes = [P, ctypes.POINTER(PlanInfo)]
         L.bf_plan_set_tile.argtypes = [P, i32, i32, i32, i32, i32]
+        L.bf_plan_set_output_scale.argtypes = [P, ctypes.c_float]
         L.bf_plan_tile_candidates.argtypes = [P, P, i32]
         L.bf_batch_tile_candidates.argtypes = [P, P, i32]
         L.bf_plan_destroy.argtypes = [P]
@@ -129,15 +132,19 @@ class Plan:
     """One beam set: N antennas, C channels, B beams, T samples per block,
     integration I.  Owns the device weights (see ``bf_plan_create_ex``).
     ``input_bits``: 8 (int8 [C][T][N][2]) or 4 (uint8 [C][T][N], real part in
-    the high nibble, imaginary part in the low nibble)."""
+    the high nibble, imaginary part in the low nibble).  ``output``: "power"
+    (float32 [C][B][T/I]) or "complex" (float16 [C][B][T][2], I == 1)."""
 
     def __init__(self, n_antennas: int, n_channels: int, n_beams: int, n_samples: int,
                  integration: int = 1, precision: str | int = "fp32",
-                 accumulate: bool = False, input_bits: int = 8):
+                 accumulate: bool = False, input_bits: int = 8, output: str = "power"):
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         if input_bits not in (4, 8):
             raise ValueError("input_bits must be 4 or 8")
+        if output not in ("power", "complex"):
+            raise ValueError("output must be 'power' or 'complex'")
         flags = (ACCUMULATE if accumulate else 0) | (INPUT_4BIT if input_bits == 4 else 0)
+        flags |= OUTPUT_COMPLEX if output == "complex" else 0
         h = ctypes.c_void_p()
         _check(lib().bf_plan_create_ex(ctypes.byref(h), n_antennas, n_channels, n_beams,
                                        n_samples, integration, prec, flags), "bf_plan_create_ex")
@@ -146,6 +153,7 @@ class Plan:
                                                   integration)
         self.precision = prec
         self.input_bits = input_bits
+        self.output = output
 
     @property
     def x_shape(self) -> tuple:
@@ -158,6 +166,23 @@ class Plan:
     def x_dtype(self):
         import torch
         return torch.uint8 if self.input_bits == 4 else torch.int8
+
+    @property
+    def p_shape(self) -> tuple:
+        """Shape of one block's output for this plan's output form."""
+        if self.output == "complex":
+            return (self.C, self.B, self.T, 2)
+        return (self.C, self.B, self.windows)
+
+    @property
+    def p_dtype(self):
+        import torch
+        return torch.float16 if self.output == "complex" else torch.float32
+
+    def set_output_scale(self, scale: float) -> None:
+        """Factor applied to complex beams before their FP16 rounding."""
+        _check(lib().bf_plan_set_output_scale(self.handle, float(scale)),
+               "bf_plan_set_output_scale")
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -195,15 +220,15 @@ class Plan:
         if x.dtype != self.x_dtype or tuple(x.shape) != self.x_shape:
             raise ValueError(f"x must be {self.x_dtype} {list(self.x_shape)}, "
                              f"got {x.dtype} {tuple(x.shape)}")
-        if p.dtype != torch.float32 or tuple(p.shape) != (self.C, self.B, self.windows):
-            raise ValueError(f"p must be float32 [{self.C}][{self.B}][{self.windows}], "
+        if p.dtype != self.p_dtype or tuple(p.shape) != self.p_shape:
+            raise ValueError(f"p must be {self.p_dtype} {list(self.p_shape)}, "
                              f"got {p.dtype} {tuple(p.shape)}")
         for t in (x, p):
             if not t.is_cuda or not t.is_contiguous():
                 raise ValueError("x and p must be contiguous device tensors")
 
     def run(self, x, p, stream=None) -> None:
-        """Enqueue one block: x (``x_shape``, ``x_dtype``) -> p float32 [C][B][T/I]."""
+        """Enqueue one block: x (``x_shape``, ``x_dtype``) -> p (``p_shape``, ``p_dtype``)."""
         self.check_io(x, p)
         _check(lib().bf_run(self.handle, x.data_ptr(), p.data_ptr(), _stream_ptr(stream)),
                "bf_run")

@@ -27,6 +27,8 @@ struct bf_plan_s {
   int mode = 0;
   bool vec16 = true;
   bool in4 = false;  // 4-bit complex input (one byte per antenna sample)
+  bool cx = false;   // complex beam output (FP16 pairs) instead of power
+  float out_scale = 1.0f;
   Tile tile{4, 1, 1};
   int32_t sgw = 1;
   int device = 0;
@@ -116,15 +118,23 @@ const Tile kIn4Tiles[] = {
     BF_TILE_LIST_IN4
 #undef BF_TILE
 };
+const Tile kCxTiles[] = {
+#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
+    BF_TILE_LIST_CX
+#undef BF_TILE
+};
 
 bool same_tile(const Tile& a, const Tile& b) {
   return a.mt == b.mt && a.nbt == b.nbt && a.nbp == b.nbp && a.kres == b.kres;
 }
 
-// The single-set variants compiled for a plan's input format and row width.
+// The single-set variants compiled for a plan's output, input format and
+// row width.
 template <class F>
 void for_each_tile(const bf_plan_s* p, F f) {
-  if (p->in4)
+  if (p->cx && p->vec16)
+    for (const Tile& x : kCxTiles) f(x);
+  else if (p->in4)
     for (const Tile& x : kIn4Tiles) f(x);
   else if (p->vec16)
     for (const Tile& x : kVecTiles) f(x);
@@ -169,15 +179,16 @@ void choose_tile(bf_plan_s* p) {
   if (!p->vec16) {
     t = nbt == 8 ? Tile{4, 8, 2, 0} : Tile{4, 1, 1, 0};
   } else if (nch == 1 && nbt >= 4) {
-    t = (p->prec == BF_FP32 || p->in4) ? Tile{4, nbt, 1, 1} : Tile{8, nbt, 1, 1};
+    t = (p->prec == BF_FP32 || p->in4 || p->cx) ? Tile{4, nbt, 1, 1} : Tile{8, nbt, 1, 1};
   } else if (nch == 2 && nbt >= 4) {
     t = Tile{4, nbt, 1, 2};
   } else {
     t = nbt >= 4 ? Tile{4, nbt, 2, 0} : nbt == 2 ? Tile{4, 2, 2, 0} : Tile{4, 1, 1, 0};
   }
-  // the 4-bit variants carry fewer register-resident forms: fall back to
+  // the 4-bit and complex-output variants carry fewer forms: fall back to
   // the streamed form of the same beam range
   if (!tile_ok(p, t) && nbt >= 2) t = Tile{4, nbt, 2, 0};
+  if (!tile_ok(p, t) && nbt >= 2) t = Tile{4, 2, 2, 0};
   if (!tile_ok(p, t)) t = Tile{4, 1, 1, 0};
   int32_t G, QI, SG;
   schedule(p->I, p->T, &G, &QI, &SG);
@@ -223,6 +234,7 @@ Prob make_prob(const bf_plan_s* p, const int8_t* x, float* out, int64_t unit_beg
   // share of the channel block) serve every beam range from L2 if those
   // units run together, whereas one beam range's weights are small
   q.br_fast = q.nbr > 1 ? 1 : 0;
+  q.out_scale = p->out_scale;
   return q;
 }
 
@@ -343,7 +355,10 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
       return BF_ERR_INVALID_ARG;
     if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
       return BF_ERR_INVALID_ARG;
-    if (flags & ~(BF_ACCUMULATE | BF_INPUT_4BIT)) return BF_ERR_INVALID_ARG;
+    if (flags & ~(BF_ACCUMULATE | BF_INPUT_4BIT | BF_OUTPUT_COMPLEX)) return BF_ERR_INVALID_ARG;
+    // complex beams are per sample and overwrite their output
+    if ((flags & BF_OUTPUT_COMPLEX) && (I != 1 || (flags & BF_ACCUMULATE)))
+      return BF_ERR_INVALID_ARG;
     // 4-bit rows are read 8 bytes (8 antennas) at a time
     if ((flags & BF_INPUT_4BIT) && N % 8 != 0) return BF_ERR_UNSUPPORTED;
     bf_plan_s* p = new (std::nothrow) bf_plan_s();
@@ -360,6 +375,8 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
     p->mode = mode_of(I);
     p->vec16 = (2 * N) % 16 == 0;
     p->in4 = (flags & BF_INPUT_4BIT) != 0;
+    p->cx = (flags & BF_OUTPUT_COMPLEX) != 0;
+    if (p->cx) p->mode = bf::kModeCx;
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;
       return BF_ERR_HIP;
@@ -586,6 +603,13 @@ int bf_plan_set_tile(bf_plan_t p, int32_t mt, int32_t nbt, int32_t nbp, int32_t 
   return BF_OK;
 }
 
+int bf_plan_set_output_scale(bf_plan_t p, float scale) {
+  if (!p || !std::isfinite(scale) || !(scale > 0.0f)) return BF_ERR_INVALID_ARG;
+  if (!p->cx) return BF_ERR_STATE;
+  p->out_scale = scale;
+  return BF_OK;
+}
+
 int bf_plan_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
   if (!p || max_tiles < 0 || (max_tiles > 0 && !tiles)) return BF_ERR_INVALID_ARG;
   int32_t n = 0;
@@ -606,7 +630,7 @@ int bf_plan_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
 int bf_batch_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
   if (!p || max_tiles < 0 || (max_tiles > 0 && !tiles)) return BF_ERR_INVALID_ARG;
   int32_t n = 0;
-  if (!p->vec16) return 0;
+  if (!p->vec16 || p->cx) return 0;
   for (const Tile& t : kMultiTiles) {
     if (!tile_ok(p, t)) continue;
     if (n < max_tiles) {
@@ -631,7 +655,7 @@ int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n) {
       if (!plans[i]->weights_set) return BF_ERR_STATE;
       const bf_plan_s* a = plans[0];
       const bf_plan_s* b = plans[i];
-      if (b->prec != a->prec || b->mode != a->mode || b->vec16 != a->vec16 ||
+      if (b->cx || b->prec != a->prec || b->mode != a->mode || b->vec16 != a->vec16 ||
           b->in4 != a->in4 || b->device != a->device)
         return BF_ERR_UNSUPPORTED;
     }
@@ -756,7 +780,7 @@ int bf_table_set(bf_table_t t, const bf_plan_t* plans, const int8_t* const* x, f
     for (int i = 0; i < n; ++i) {
       const bf_plan_s* p = plans[i];
       if (!p) return BF_ERR_INVALID_ARG;
-      if (p->N != t->N || p->I != t->I || p->prec != t->prec || p->in4 != t->in4 ||
+      if (p->cx || p->N != t->N || p->I != t->I || p->prec != t->prec || p->in4 != t->in4 ||
           p->device != t->device)
         return BF_ERR_UNSUPPORTED;
     }

@@ -14,14 +14,15 @@ constexpr int kChunk = 64;      // real K elements (32 antennas) per chunk
 constexpr int kLdsPad = 16;     // bytes added to each LDS weight row
 
 // Integration classes; each is a separate kernel instantiation:
-// I == 1, I == 2, I >= 3 with I % 4 != 0 (padded windows), I % 4 == 0.
-enum Mode : int { kModeI1 = 0, kModeI2 = 1, kModeGen = 2, kModeGen4 = 3 };
+// I == 1, I == 2, I >= 3 with I % 4 != 0 (padded windows), I % 4 == 0;
+// and complex beam output (no detection, I == 1 row mapping).
+enum Mode : int { kModeI1 = 0, kModeI2 = 1, kModeGen = 2, kModeGen4 = 3, kModeCx = 4 };
 
 // One beam set (plan) inside a launch.  Lives in the kernel-argument
 // segment, so every field is read through scalar loads.
 struct Prob {
-  const int8_t* x;    // [C][T][N][2] int8
-  float* p;           // [C][B][W] float
+  const int8_t* x;    // [C][T][N][2] int8 (4-bit input: [C][T][N] bytes)
+  float* p;           // [C][B][W] float; complex output: [C][B][T] pairs of FP16
   const void* w;      // [C][Bpad][2][Kpad] storage precision (operand layout)
   int64_t T;          // samples per block
   int64_t W;          // windows = T / I
@@ -40,6 +41,7 @@ struct Prob {
   int32_t br_fast;    // unit order (c, tr, br) instead of (c, br, tr): the beam
                       // ranges of one time range run back to back and share its
                       // voltages through L2
+  float out_scale;    // complex output: factor applied to B before FP16 rounding
 };
 
 struct Launch {
@@ -73,6 +75,11 @@ struct Tile {
 // Variants compiled into the persistent batching kernel (16-byte loads).
 // (MT = 8 variants are left out: their register use would halve the
 // kernel's occupancy for every set.)
+// Variants compiled for complex beam output (16-byte rows; byte-load plans
+// use the generic list).
+#define BF_TILE_LIST_CX                                                           \
+  BF_TILE(4, 8, 1, 1) BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 8, 2, 0)  \
+  BF_TILE(4, 2, 2, 0) BF_TILE(4, 1, 1, 0)
 #define BF_TILE_LIST_MULTI                                                        \
   BF_TILE(4, 8, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0)  \
   BF_TILE(4, 1, 1, 0)

@@ -1,0 +1,154 @@
+"""Complex (electric-field) beam output on the GPU: B = sum_n W X per
+channel, beam and sample (Sec. 2.1) written as FP16 (re, im) pairs, beam-major
+(the S-engine's complex beam words, Sec. 1.1), instead of detected power.
+
+Reference: the FP64 oracle's complex beams times the output scale, clamped to
++-65504 and rounded to FP16 by numpy.  FP32 path: every component within one
+FP16 unit in the last place of the reference plus 1e-5 of the beam's RMS
+(the FP32 sum may sit on the other side of a rounding boundary); FP16/BF16
+paths: the precision form's tolerance (2e-3 / 1e-2) relative to |B| plus
+the beam's RMS, per element and per beam normwise.  Integer weights and
+small integer inputs make every beam an integer that FP16 holds exactly:
+bit-exact in all precisions."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_4907_amd import bf, synth
+from tests.gpu_util import run_plan
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp16": 2e-3, "bf16": 1e-2}
+
+
+def run_cx(plan, x, dev):
+    import torch
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    p = torch.full(plan.p_shape, float("nan"), dtype=torch.float16, device=dev)
+    plan.run(xd, p)
+    torch.cuda.synchronize()
+    out = p.cpu().numpy().astype(np.float64)
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def reference(W, x, scale):
+    b = oracle.beams(W, x) * scale
+    f = lambda v: np.clip(v, -65504.0, 65504.0).astype(np.float16).astype(np.float64)
+    return b, f(b.real) + 1j * f(b.imag)
+
+
+def check(got, exact, prec, what):
+    assert np.all(np.isfinite(got)), what
+    rms = np.sqrt(np.mean(np.abs(exact) ** 2, axis=-1, keepdims=True))
+    d = got - exact
+    if prec == "fp32":
+        r16 = np.clip(exact, -65504, 65504)
+        ulp = lambda v: np.spacing(np.abs(v).astype(np.float16)).astype(np.float64)
+        lim_re = ulp(r16.real) + 1e-5 * rms
+        lim_im = ulp(r16.imag) + 1e-5 * rms
+        assert np.all(np.abs(d.real) <= lim_re), (what, np.max(np.abs(d.real) / lim_re))
+        assert np.all(np.abs(d.imag) <= lim_im), (what, np.max(np.abs(d.imag) / lim_im))
+        tol = 1e-3
+    else:
+        tol = TOL[prec]
+        e = np.abs(d) / (np.abs(exact) + rms)
+        assert e.max() <= tol, (what, e.max())
+    nw = np.linalg.norm(d, axis=-1) / np.maximum(np.linalg.norm(exact, axis=-1), 1e-300)
+    assert nw.max() <= tol, (what, nw.max())
+
+
+SHAPES = [  # N, C, B, T
+    (32, 2, 128, 1024), (32, 3, 37, 100), (8, 2, 16, 64), (64, 2, 40, 256), (256, 1, 20, 96),
+    (5, 2, 9, 33), (17, 1, 33, 48), (24, 2, 130, 200),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"N{s[0]}C{s[1]}B{s[2]}T{s[3]}" for s in SHAPES])
+def test_complex_output_matches_oracle(gpu, shape, prec):
+    N, C, B, T = shape
+    print(f"complex {shape} {prec}", flush=True)
+    g = np.random.default_rng(sum(shape) + 3 * len(prec))
+    pos = synth.disc_positions(N, 150.0, g)
+    dirs = synth.random_dirs(B, g)
+    freqs = np.linspace(401e6, 415e6, C)
+    x = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+    scale = 1.0 / np.sqrt(N)
+    with bf.Plan(N, C, B, T, 1, precision=prec, output="complex") as plan:
+        plan.set_weights(pos, dirs, freqs)
+        plan.set_output_scale(scale)
+        got = run_cx(plan, x, gpu)
+    exact, _ = reference(oracle.weights(pos, dirs, freqs), x, scale)
+    check(got, exact, prec, f"{shape} {prec}")
+
+
+def test_complex_integer_exact_every_tile(gpu):
+    g = np.random.default_rng(40)
+    N, C, B, T = 64, 2, 48, 512
+    units = np.array([1, -1, 1j, -1j])
+    W = units[g.integers(0, 4, (C, B, N))]
+    x = g.integers(-7, 8, (C, T, N, 2)).astype(np.int8)
+    _, ref16 = reference(W, x, 1.0)
+    for prec in ("fp32", "fp16", "bf16"):
+        with bf.Plan(N, C, B, T, 1, precision=prec, output="complex") as plan:
+            plan.set_weights_raw(W)
+            got = run_cx(plan, x, gpu)
+            assert np.array_equal(got, ref16), prec
+            for i, t in enumerate(plan.tile_candidates()):
+                plan.set_tile(*t, [4, 8, 12][i % 3])  # a multiple of MT at I = 1
+                assert np.array_equal(run_cx(plan, x, gpu), ref16), (prec, t)
+
+
+def test_complex_4bit_equals_int8_and_saturates(gpu):
+    g = np.random.default_rng(41)
+    N, C, B, T = 32, 2, 64, 512
+    pos = synth.grid_positions(4, 8, 10.0, 20.0)
+    dirs = synth.random_dirs(B, g)
+    freqs = np.array([402e6, 411e6])
+    x4 = g.integers(0, 256, (C, T, N)).astype(np.uint8)
+    x8 = oracle.unpack4(x4)
+    for prec in ("fp16", "fp32"):
+        with bf.Plan(N, C, B, T, 1, precision=prec, output="complex", input_bits=4) as p4, \
+                bf.Plan(N, C, B, T, 1, precision=prec, output="complex") as p8:
+            p4.set_weights(pos, dirs, freqs)
+            p8.set_weights(pos, dirs, freqs)
+            a = run_cx(p4, x4, gpu)
+            p8.set_tile(*p4.tile())
+            b = run_cx(p8, x8, gpu)
+            assert np.array_equal(a, b), prec
+            # a scale that drives most beams past the FP16 range: clamped, never inf
+            p4.set_output_scale(4096.0)
+            big = run_cx(p4, x4, gpu)
+        exact, ref16 = reference(oracle.weights(pos, dirs, freqs), x8, 4096.0)
+        assert np.all(np.isfinite(big)) and np.abs(big.real).max() == 65504.0
+        sat = (np.abs(exact.real) > 70000) | (np.abs(exact.imag) > 70000)
+        assert sat.mean() > 0.2
+        assert np.array_equal(big[sat & (np.abs(exact.real) > 70000)].real,
+                              ref16[sat & (np.abs(exact.real) > 70000)].real)
+
+
+def test_complex_rejections(gpu):
+    import torch
+    g = np.random.default_rng(42)
+    pos = synth.grid_positions(4, 8, 10.0, 20.0)
+    with bf.Plan(32, 1, 16, 64, 1, output="complex") as pc, bf.Plan(32, 1, 16, 64, 1) as pp:
+        for p in (pc, pp):
+            p.set_weights(pos, synth.random_dirs(16, g), [403e6])
+        with pytest.raises(bf.BfError) as e:
+            pp.set_output_scale(2.0)
+        assert e.value.status == bf.ERR_STATE
+        with pytest.raises(bf.BfError) as e:
+            pc.set_output_scale(float("inf"))
+        assert e.value.status == bf.ERR_INVALID_ARG
+        with pytest.raises(bf.BfError) as e:
+            bf.Batch([pp, pc])
+        assert e.value.status == bf.ERR_UNSUPPORTED
+        table = bf.Table(32, 1, "fp32")
+        x = torch.zeros((1, 64, 32, 2), dtype=torch.int8, device=gpu)
+        out = torch.empty(pc.p_shape, dtype=torch.float16, device=gpu)
+        with pytest.raises(bf.BfError) as e:
+            table.set([pc], [x], [out])
+        assert e.value.status == bf.ERR_UNSUPPORTED
+        table.destroy()
+        with pytest.raises(ValueError):  # a power buffer for a complex plan
+            pc.run(x, torch.empty((1, 16, 64), device=gpu))

@@ -301,3 +301,57 @@ def test_4bit_block_closed_forms():
         x4 = np.full((1, T, N), byte, dtype=np.uint8)
         P = oracle.beamform(W, oracle.unpack4(x4), I)
         np.testing.assert_array_equal(P, I * N * N * (np.real(v) ** 2 + np.imag(v) ** 2))
+
+
+# --- complex beams before detection (Sec. 2.1; E-field output, Sec. 1.1) -----
+
+def test_beams_brute_force_tiny():
+    g = np.random.default_rng(15)
+    for N, C, B, T in [(1, 1, 1, 1), (3, 2, 3, 5), (4, 1, 2, 3)]:
+        pos = g.uniform(-50, 50, (N, 3))
+        dirs = synth.random_dirs(B, g)
+        freqs = g.uniform(300e6, 500e6, C)
+        x = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+        Bm = oracle.beams(oracle.weights(pos, dirs, freqs), x)
+        assert Bm.shape == (C, B, T)
+        for c in range(C):
+            for b in range(B):
+                for t in range(T):
+                    beam = 0j
+                    for n in range(N):
+                        delay = sum(dirs[b][j] * pos[n][j] for j in range(3)) / C0
+                        wt = complex(math.cos(2 * math.pi * freqs[c] * delay),
+                                     -math.sin(2 * math.pi * freqs[c] * delay))
+                        beam += wt * complex(int(x[c, t, n, 0]), int(x[c, t, n, 1]))
+                    assert abs(Bm[c, b, t] - beam) <= 1e-12 * max(1.0, abs(beam))
+
+
+def test_beams_dft_weights_are_an_fft():
+    """With W[b][n] = exp(-2 pi i b n / N) the beams of each sample are the
+    DFT of its antenna vector (numpy's FFT)."""
+    N = 16
+    n = np.arange(N)
+    W = np.exp(-2j * np.pi * np.outer(n, n) / N)[None]
+    g = np.random.default_rng(16)
+    x = g.integers(-128, 128, (1, 12, N, 2)).astype(np.int8)
+    Bm = oracle.beams(W, x)[0]                               # [B][T]
+    xc = x[0, ..., 0].astype(float) + 1j * x[0, ..., 1]      # [T][N]
+    np.testing.assert_allclose(Bm.T, np.fft.fft(xc, axis=1), atol=1e-9)
+
+
+def test_beams_on_beam_plane_wave_and_power():
+    """A plane wave from beam b's direction sums to N s(t) on that beam (the
+    phase of Eq. 1 cancels), and |beams|^2 summed over windows is the
+    detected, integrated power."""
+    w = synth.paper()
+    f = w.freqs[[3, 900]]
+    k = w.dirs[21]
+    T = 32
+    s = 3.0 * np.exp(2j * np.pi * 0.05 * np.arange(T))
+    x = np.stack([plane_wave(w.pos, k, fc, s) for fc in f])
+    W = oracle.weights(w.pos, w.dirs[[21, 5]], f)
+    Bm = oracle.beams(W, x)
+    np.testing.assert_allclose(Bm[:, 0], 32 * np.broadcast_to(s, (2, T)), atol=1e-9)
+    P = oracle.beamform(W, x, 4)
+    np.testing.assert_allclose(P, (np.abs(Bm) ** 2).reshape(2, 2, T // 4, 4).sum(-1),
+                               rtol=1e-12)
