@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--input-bits", type=int, default=8, choices=[8, 4],
                     help="voltage format: int8 pairs, or 4-bit pairs packed one per byte")
+    ap.add_argument("--output", default="power", choices=["power", "complex"],
+                    help="detected integrated power, or complex FP16 beams (integration 1)")
     ap.add_argument("--workload", default="paper",
                     choices=["paper", "small", "precision", "serve", "batch"])
     ap.add_argument("--blocks", type=int, default=200, help="serve: blocks to stream")
@@ -104,13 +106,13 @@ def workload(name):
     return {"paper": synth.paper, "small": synth.small, "precision": synth.precision}[name]()
 
 
-def algorithmic_bytes(w, prec) -> float:
+def algorithmic_bytes(w, prec, output="power") -> float:
     """Bytes one launch must move at minimum: every voltage once, every
-    weight once, every output window once."""
+    weight once, every output window (or complex FP16 sample) once."""
     es = 4 if prec == "fp32" else 2
     x = w.n_chan * w.n_samples * w.n_ant * (1 if w.input_bits == 4 else 2)
     wt = w.n_chan * w.n_beams * w.n_ant * 2 * es
-    p = w.n_chan * w.n_beams * (w.n_samples // w.integration) * 4
+    p = w.n_chan * w.n_beams * (w.n_samples // w.integration) * 4  # f32 power or 2 x f16
     return float(x + wt + p)
 
 
@@ -404,6 +406,9 @@ def main():
     if a.input_bits == 4:
         from paper_1412_4907_amd import synth
         w = synth.four_bit(w)
+    if a.output == "complex":
+        import dataclasses
+        w = dataclasses.replace(w, name=w.name + "_complex", integration=1)
     t0 = time.perf_counter()
     x = w.voltages(workers=16)
     gen_s = time.perf_counter() - t0
@@ -413,9 +418,11 @@ def main():
 
     def leg(prec, steps, warmup):
         plan = bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration, precision=prec,
-                       input_bits=w.input_bits)
+                       input_bits=w.input_bits, output=a.output)
         plan.set_weights(w.pos, w.dirs, w.freqs)
-        p = torch.empty((w.n_chan, w.n_beams, windows), dtype=torch.float32, device=dev)
+        if a.output == "complex":
+            plan.set_output_scale(1.0 / np.sqrt(w.n_ant))
+        p = torch.empty(plan.p_shape, dtype=plan.p_dtype, device=dev)
         # tile shape from the autotuner's cache, else tuned now (untimed)
         if a.retune or tune.apply_cached(plan) is None:
             tune.tune(plan, xd, p, reps=3)
@@ -443,7 +450,7 @@ def main():
     flops = w.flops
     value = flops / (ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[a.precision]
-    abytes = algorithmic_bytes(w, a.precision)
+    abytes = algorithmic_bytes(w, a.precision, a.output)
     chan_rate = 16e6 / 1024  # channel sample rate of every workload here
     block_s = w.n_samples / chan_rate
     kernel_key = f"beamform/{w.name}/{a.precision}"
@@ -462,7 +469,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: N={w.n_ant} antennas, C={w.n_chan} channels, "
                                f"B={w.n_beams} beams, T={w.n_samples} samples, I={w.integration}",
-                   "precision": a.precision, "input_bits": w.input_bits,
+                   "precision": a.precision, "input_bits": w.input_bits, "output": a.output,
                    "n_antennas": w.n_ant, "n_channels": w.n_chan,
                    "n_beams": w.n_beams, "n_samples": w.n_samples, "integration": w.integration,
                    "tile": {"mt": info["tile_mt"], "nbt": info["tile_nbt"],
@@ -490,7 +497,7 @@ def main():
             per2, total2, _ = leg(prec, a.steps, a.warmup)
             ms2 = total2 / a.steps
             v2 = flops / (ms2 * 1e-3) / 1e12
-            ab2 = algorithmic_bytes(w, prec)
+            ab2 = algorithmic_bytes(w, prec, a.output)
             extra[prec] = {"tflops": round(v2, 3), "ms_per_step": round(ms2, 4),
                            "mfma_peak_frac": round(v2 / PEAK_TFLOPS[prec], 4),
                            "hbm_frac": round(ab2 / (ms2 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),

@@ -26,13 +26,14 @@ def cache_path() -> str:
 
 
 def shape_key(plan, arch: str = "gfx950") -> str:
-    """Tile choice depends on precision, input format, N, B, I and the block
+    """Tile choice depends on precision, input and output form, N, B, I and the block
     length; C and T enter through the number of work units (bucketed by
     powers of 2)."""
     import math
     cb = 1 << int(math.log2(max(1, plan.C)))
     tb = 1 << int(math.log2(max(1, plan.T)))
     fmt = "/in4" if getattr(plan, "input_bits", 8) == 4 else ""
+    fmt += "/cx" if getattr(plan, "output", "power") == "complex" else ""
     return f"{arch}/p{plan.precision}/N{plan.N}/B{plan.B}/I{plan.I}/C~{cb}/T~{tb}{fmt}"
 
 

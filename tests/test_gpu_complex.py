@@ -152,3 +152,39 @@ def test_complex_rejections(gpu):
         table.destroy()
         with pytest.raises(ValueError):  # a power buffer for a complex plan
             pc.run(x, torch.empty((1, 16, 64), device=gpu))
+
+
+# Shapes the register-resident pipelined form serves (full beam ranges, every
+# K chunk in registers, T % 4 == 0): bit for bit the streamed form, which
+# never takes it, and the oracle within the precision's tolerance.
+FAST = [  # N, C, B, T, tile
+    (32, 2, 128, 1024, (4, 8, 1, 1, 4)), (16, 2, 64, 512, (4, 4, 1, 1, 8)),
+    (24, 1, 256, 768, (4, 8, 1, 1, 4)), (64, 2, 128, 512, (4, 8, 1, 2, 4)),
+]
+
+
+@pytest.mark.parametrize("input_bits", [8, 4])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("case", FAST, ids=[f"N{s[0]}B{s[2]}T{s[3]}" for s in FAST])
+def test_complex_pipelined_form(gpu, case, prec, input_bits):
+    N, C, B, T, tile = case
+    print(f"complex pipelined {case} {prec} {input_bits}-bit", flush=True)
+    g = np.random.default_rng(N + B + T + input_bits)
+    pos = synth.disc_positions(N, 150.0, g)
+    dirs = synth.random_dirs(B, g)
+    freqs = np.linspace(402e6, 414e6, C)
+    if input_bits == 4:
+        x = g.integers(0, 256, (C, T, N)).astype(np.uint8)
+        x8 = oracle.unpack4(x)
+    else:
+        x = x8 = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+    with bf.Plan(N, C, B, T, 1, precision=prec, output="complex", input_bits=input_bits) as plan:
+        plan.set_weights(pos, dirs, freqs)
+        plan.set_output_scale(0.25)
+        plan.set_tile(*tile)
+        got = run_cx(plan, x, gpu)
+        plan.set_tile(4, 8, 2, 0, 4)
+        streamed = run_cx(plan, x, gpu)
+    assert np.array_equal(got, streamed), case
+    exact, _ = reference(oracle.weights(pos, dirs, freqs), x8, 0.25)
+    check(got, exact, prec, f"{case} {prec}")
