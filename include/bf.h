@@ -135,6 +135,37 @@ int bf_set_weights(bf_plan_t plan, const double* ant_xyz_m, const double* beam_d
                    const double* chan_freq_hz, void* stream);
 
 /*
+ * Time-varying weights (Sec. 3.2: coefficients for the next pointing are
+ * computed while the previous buffer is being beamformed; Sec. 3.1: tracking
+ * beams).  Generates weights from geometry exactly as bf_set_weights, but
+ * into a second plan-owned buffer, enqueued on `stream` (typically not the
+ * stream the runs use), so it overlaps the runs in flight.  The next bf_run
+ * or bf_batch_run of the plan (on any stream) waits on the device for this
+ * generation to finish and then reads the new weights; runs enqueued before
+ * that keep the previous ones.  The generation itself waits on the device
+ * for the runs that last read the spare buffer.  The first call allocates
+ * the spare buffer (the size of the weight buffer) and three events, kept
+ * until bf_plan_destroy.  A later bf_set_weights or bf_set_weights_raw
+ * supersedes a refresh not yet taken by a run.  The host arrays are copied
+ * before return (the call may wait for the previous weight generation of
+ * the plan to finish reading its staging area).  Plans refreshed this way
+ * are not accepted by bf_table_set (BF_ERR_UNSUPPORTED).
+ * Errors: as bf_set_weights, plus BF_ERR_OOM.
+ */
+int bf_set_weights_async(bf_plan_t plan, const double* ant_xyz_m, const double* beam_dir,
+                         const double* chan_freq_hz, void* stream);
+
+/*
+ * Sub-arraying (Sec. 3.1: an antenna mask restricts beamforming to the
+ * antennas a sub-array needs).  mask: host [N], nonzero = antenna used;
+ * NULL = every antenna.  Copied; applies to the weights generated by later
+ * bf_set_weights / bf_set_weights_async calls (a masked antenna gets zero
+ * weights, so its voltages do not enter any beam).  Errors:
+ * BF_ERR_INVALID_ARG (null plan).
+ */
+int bf_plan_set_antenna_mask(bf_plan_t plan, const uint8_t* mask);
+
+/*
  * Load arbitrary complex weights (host [C][B][N][2] double, re/im), each
  * component rounded once to the storage precision.  Synchronous (returns
  * after the device copy is complete).  Used for DFT/integer-weight tests
@@ -144,7 +175,8 @@ int bf_set_weights(bf_plan_t plan, const double* ant_xyz_m, const double* beam_d
 int bf_set_weights_raw(bf_plan_t plan, const double* weights, void* stream);
 
 /*
- * Copy the plan's rounded weights back to host [C][B][N][2] double.
+ * Copy the plan's rounded weights back to host [C][B][N][2] double: the ones
+ * the next run reads (after a pending bf_set_weights_async, those).
  * Synchronous.  Errors: BF_ERR_INVALID_ARG, BF_ERR_STATE (none set),
  * BF_ERR_HIP.
  */

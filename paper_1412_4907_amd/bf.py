@@ -26,7 +26,8 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = 0, -1, -2, -
 
 # every entry point declared in include/bf.h
 EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_plan_create",
-           "bf_plan_create_ex", "bf_set_weights", "bf_set_weights_raw", "bf_get_weights",
+           "bf_plan_create_ex", "bf_set_weights", "bf_set_weights_async",
+           "bf_plan_set_antenna_mask", "bf_set_weights_raw", "bf_get_weights",
            "bf_run", "bf_plan_info", "bf_plan_set_tile", "bf_plan_set_output_scale",
            "bf_plan_tile_candidates",
            "bf_plan_destroy", "bf_batch_create", "bf_batch_tile_candidates", "bf_batch_run",
@@ -77,6 +78,8 @@ def lib() -> ctypes.CDLL:
         L.bf_plan_create.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32]
         L.bf_plan_create_ex.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, ctypes.c_int, u32]
         L.bf_set_weights.argtypes = [P, P, P, P, P]
+        L.bf_set_weights_async.argtypes = [P, P, P, P, P]
+        L.bf_plan_set_antenna_mask.argtypes = [P, P]
         L.bf_set_weights_raw.argtypes = [P, P, P]
         L.bf_get_weights.argtypes = [P, P, P]
         L.bf_run.argtypes = [P, P, P, P]
@@ -200,6 +203,27 @@ class Plan:
         freqs = _host_f64(freqs, (self.C,))
         _check(lib().bf_set_weights(self.handle, pos.ctypes.data, dirs.ctypes.data,
                                     freqs.ctypes.data, _stream_ptr(stream)), "bf_set_weights")
+
+    def set_weights_async(self, pos, dirs, freqs, stream=None) -> None:
+        """Generate the next pointing's weights on ``stream`` into the spare
+        buffer; the plan's next run waits for them and switches over."""
+        pos = _host_f64(pos, (self.N, 3))
+        dirs = _host_f64(dirs, (self.B, 3))
+        freqs = _host_f64(freqs, (self.C,))
+        _check(lib().bf_set_weights_async(self.handle, pos.ctypes.data, dirs.ctypes.data,
+                                          freqs.ctypes.data, _stream_ptr(stream)),
+               "bf_set_weights_async")
+
+    def set_antenna_mask(self, mask=None) -> None:
+        """Antennas used by weights generated from now on (None: all)."""
+        if mask is None:
+            _check(lib().bf_plan_set_antenna_mask(self.handle, None), "bf_plan_set_antenna_mask")
+            return
+        m = np.ascontiguousarray(np.asarray(mask).astype(bool), dtype=np.uint8)
+        if m.shape != (self.N,):
+            raise ValueError(f"mask must have {self.N} entries")
+        _check(lib().bf_plan_set_antenna_mask(self.handle, m.ctypes.data),
+               "bf_plan_set_antenna_mask")
 
     def set_weights_raw(self, w, stream=None) -> None:
         w = np.asarray(w)

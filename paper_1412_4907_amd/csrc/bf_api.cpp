@@ -34,14 +34,23 @@ struct bf_plan_s {
   int device = 0;
   int n_cu = 256;
   size_t w_bytes = 0;
-  void* w_dev = nullptr;
+  void* w_dev = nullptr;  // the weights runs read
   bool weights_set = false;
   // geometry staging for bf_set_weights: pinned host + device, reused
+  // (positions, directions, frequencies, antenna mask)
   double* geo_host = nullptr;
   double* geo_dev = nullptr;
   size_t geo_count = 0;
-  hipEvent_t geo_done = nullptr;
+  hipEvent_t geo_done = nullptr;  // recorded after the last weight kernel read geo_dev
   bool geo_pending = false;
+  std::vector<double> mask;  // [N], 1 = antenna used
+  // asynchronous refresh (bf_set_weights_async): a second buffer, filled on
+  // the caller's stream while runs read w_dev; the next run waits for it and
+  // swaps.  used_cur / used_alt mark the last run that read each buffer.
+  void* w_alt = nullptr;
+  hipEvent_t w_ready = nullptr;
+  hipEvent_t used_cur = nullptr, used_alt = nullptr;
+  bool refresh_pending = false;
 };
 
 struct bf_batch_s {
@@ -325,6 +334,66 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
   return BF_OK;
 }
 
+// Validates the geometry and enqueues its upload and the weight kernel on
+// s, writing the operand-layout weights of plan p (with its antenna mask)
+// into dst.
+int generate_weights(bf_plan_s* p, const double* pos, const double* dir, const double* freq,
+                     void* dst, hipStream_t s) {
+  if (!pos || !dir || !freq) return BF_ERR_INVALID_ARG;
+  for (int64_t i = 0; i < 3 * (int64_t)p->N; ++i)
+    if (!std::isfinite(pos[i])) return BF_ERR_INVALID_ARG;
+  for (int b = 0; b < p->B; ++b) {
+    const double* d = dir + 3 * b;
+    if (!std::isfinite(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2]))
+      return BF_ERR_INVALID_ARG;
+    double nrm = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (std::fabs(nrm - 1.0) > 1e-9) return BF_ERR_INVALID_ARG;
+  }
+  for (int c = 0; c < p->C; ++c)
+    if (!std::isfinite(freq[c]) || !(freq[c] > 0.0)) return BF_ERR_INVALID_ARG;
+  // the previous weight kernel must have finished reading the staging area
+  if (p->geo_pending) {
+    hipError_t e = hipEventSynchronize(p->geo_done);
+    if (e != hipSuccess) return from_hip(e);
+    p->geo_pending = false;
+  }
+  double* h = p->geo_host;
+  const int N = p->N, B = p->B, C = p->C;
+  std::memcpy(h, pos, sizeof(double) * 3 * N);
+  std::memcpy(h + 3 * N, dir, sizeof(double) * 3 * B);
+  std::memcpy(h + 3 * N + 3 * B, freq, sizeof(double) * C);
+  std::memcpy(h + 3 * N + 3 * B + C, p->mask.data(), sizeof(double) * N);
+  hipError_t e = hipMemcpyAsync(p->geo_dev, h, p->geo_count * sizeof(double),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return from_hip(e);
+  const double* d = p->geo_dev;
+  e = bf::launch_weights_geom(p->prec, d, d + 3 * N, d + 3 * N + 3 * B, d + 3 * N + 3 * B + C, N,
+                              C, B, p->Bpad, p->Kpad, dst, s);
+  if (e != hipSuccess) return from_hip(e);
+  e = hipEventRecord(p->geo_done, s);
+  if (e != hipSuccess) return from_hip(e);
+  p->geo_pending = true;
+  return BF_OK;
+}
+
+// A run on stream s is about to read the plan's weights: take a finished
+// asynchronous refresh (the stream waits for it) and swap buffers.
+hipError_t take_refresh(bf_plan_s* p, hipStream_t s) {
+  if (!p->refresh_pending) return hipSuccess;
+  hipError_t e = hipStreamWaitEvent(s, p->w_ready, 0);
+  if (e != hipSuccess) return e;
+  std::swap(p->w_dev, p->w_alt);
+  std::swap(p->used_cur, p->used_alt);
+  p->refresh_pending = false;
+  p->weights_set = true;
+  return hipSuccess;
+}
+
+// After a launch on s that read the plan's current buffer.
+hipError_t mark_used(bf_plan_s* p, hipStream_t s) {
+  return p->used_cur ? hipEventRecord(p->used_cur, s) : hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -396,7 +465,8 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
     }
     // no clearing: both weight kernels write every element of the buffer
     // (padding included), and nothing reads it before one of them has run
-    p->geo_count = (size_t)3 * N + (size_t)3 * B + (size_t)C;
+    p->geo_count = (size_t)3 * N + (size_t)3 * B + (size_t)C + (size_t)N;
+    p->mask.assign(N, 1.0);
     e = hipHostMalloc((void**)&p->geo_host, p->geo_count * sizeof(double), 0);
     if (e == hipSuccess) e = hipMalloc(&p->geo_dev, p->geo_count * sizeof(double));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->geo_done, hipEventDisableTiming);
@@ -426,6 +496,10 @@ int bf_plan_destroy(bf_plan_t p) {
     if (p->geo_dev) (void)hipFree(p->geo_dev);
     if (p->geo_host) (void)hipHostFree(p->geo_host);
     if (p->geo_done) (void)hipEventDestroy(p->geo_done);
+    if (p->w_alt) (void)hipFree(p->w_alt);
+    if (p->w_ready) (void)hipEventDestroy(p->w_ready);
+    if (p->used_cur) (void)hipEventDestroy(p->used_cur);
+    if (p->used_alt) (void)hipEventDestroy(p->used_alt);
     (void)hipSetDevice(dev);
     delete p;
     return BF_OK;
@@ -437,44 +511,51 @@ int bf_plan_destroy(bf_plan_t p) {
 int bf_set_weights(bf_plan_t p, const double* pos, const double* dir, const double* freq,
                    void* stream) {
   try {
-    if (!p || !pos || !dir || !freq) return BF_ERR_INVALID_ARG;
-    for (int64_t i = 0; i < 3 * (int64_t)p->N; ++i)
-      if (!std::isfinite(pos[i])) return BF_ERR_INVALID_ARG;
-    for (int b = 0; b < p->B; ++b) {
-      const double* d = dir + 3 * b;
-      if (!std::isfinite(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2]))
-        return BF_ERR_INVALID_ARG;
-      double nrm = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      if (std::fabs(nrm - 1.0) > 1e-9) return BF_ERR_INVALID_ARG;
-    }
-    for (int c = 0; c < p->C; ++c)
-      if (!std::isfinite(freq[c]) || !(freq[c] > 0.0)) return BF_ERR_INVALID_ARG;
+    if (!p) return BF_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    // the previous upload must have left the pinned staging area
-    if (p->geo_pending) {
-      hipError_t e = hipEventSynchronize(p->geo_done);
-      if (e != hipSuccess) return from_hip(e);
-      p->geo_pending = false;
-    }
-    double* h = p->geo_host;
-    std::memcpy(h, pos, sizeof(double) * 3 * p->N);
-    std::memcpy(h + 3 * p->N, dir, sizeof(double) * 3 * p->B);
-    std::memcpy(h + 3 * p->N + 3 * p->B, freq, sizeof(double) * p->C);
-    hipError_t e = hipMemcpyAsync(p->geo_dev, h, p->geo_count * sizeof(double),
-                                  hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return from_hip(e);
-    e = hipEventRecord(p->geo_done, s);
-    if (e != hipSuccess) return from_hip(e);
-    p->geo_pending = true;
-    const double* d = p->geo_dev;
-    e = bf::launch_weights_geom(p->prec, d, d + 3 * p->N, d + 3 * p->N + 3 * p->B, p->N, p->C,
-                                p->B, p->Bpad, p->Kpad, p->w_dev, s);
-    if (e != hipSuccess) return from_hip(e);
+    const int st = generate_weights(p, pos, dir, freq, p->w_dev, s);
+    if (st != BF_OK) return st;
+    p->refresh_pending = false;  // superseded
     p->weights_set = true;
     return BF_OK;
   } catch (...) {
     return BF_ERR_HIP;
   }
+}
+
+int bf_set_weights_async(bf_plan_t p, const double* pos, const double* dir, const double* freq,
+                         void* stream) {
+  try {
+    if (!p) return BF_ERR_INVALID_ARG;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!p->w_alt) {
+      hipError_t e = hipMalloc(&p->w_alt, p->w_bytes);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->w_ready, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->used_cur, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->used_alt, hipEventDisableTiming);
+      if (e != hipSuccess) return from_hip(e);
+    }
+    // the runs that read the spare buffer must have finished (an event never
+    // recorded is complete), and a refresh not yet taken is overwritten in
+    // order after itself
+    hipError_t e = hipStreamWaitEvent(s, p->used_alt, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->w_ready, 0);
+    if (e != hipSuccess) return from_hip(e);
+    const int st = generate_weights(p, pos, dir, freq, p->w_alt, s);
+    if (st != BF_OK) return st;
+    e = hipEventRecord(p->w_ready, s);
+    if (e != hipSuccess) return from_hip(e);
+    p->refresh_pending = true;
+    return BF_OK;
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
+int bf_plan_set_antenna_mask(bf_plan_t p, const uint8_t* mask) {
+  if (!p) return BF_ERR_INVALID_ARG;
+  for (int n = 0; n < p->N; ++n) p->mask[n] = (!mask || mask[n]) ? 1.0 : 0.0;
+  return BF_OK;
 }
 
 int bf_set_weights_raw(bf_plan_t p, const double* w, void* stream) {
@@ -494,6 +575,7 @@ int bf_set_weights_raw(bf_plan_t p, const double* w, void* stream) {
     (void)hipFree(dw);
     if (e != hipSuccess) return from_hip(e);
     if (e2 != hipSuccess) return from_hip(e2);
+    p->refresh_pending = false;  // superseded
     p->weights_set = true;
     return BF_OK;
   } catch (...) {
@@ -504,10 +586,14 @@ int bf_set_weights_raw(bf_plan_t p, const double* w, void* stream) {
 int bf_get_weights(bf_plan_t p, double* out, void* stream) {
   try {
     if (!p || !out) return BF_ERR_INVALID_ARG;
-    if (!p->weights_set) return BF_ERR_STATE;
+    if (!p->weights_set && !p->refresh_pending) return BF_ERR_STATE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::vector<uint8_t> buf(p->w_bytes);
-    hipError_t e = hipMemcpyAsync(buf.data(), p->w_dev, p->w_bytes, hipMemcpyDeviceToHost, s);
+    // the weights the next run reads: a pending refresh once it is written
+    const void* src = p->refresh_pending ? p->w_alt : p->w_dev;
+    hipError_t e = p->refresh_pending ? hipStreamWaitEvent(s, p->w_ready, 0) : hipSuccess;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(buf.data(), src, p->w_bytes, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return from_hip(e);
     auto val = [&](size_t idx) -> double {
@@ -548,7 +634,10 @@ int bf_get_weights(bf_plan_t p, double* out, void* stream) {
 int bf_run(bf_plan_t p, const int8_t* x, float* out, void* stream) {
   try {
     if (!p || !x || !out || !aligned16(x) || !aligned16(out)) return BF_ERR_INVALID_ARG;
-    if (!p->weights_set) return BF_ERR_STATE;
+    if (!p->weights_set && !p->refresh_pending) return BF_ERR_STATE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = take_refresh(p, s);
+    if (e != hipSuccess) return from_hip(e);
     Launch L;
     std::memset(&L, 0, sizeof(L));
     L.prob[0] = make_prob(p, x, out, 0);
@@ -558,9 +647,9 @@ int bf_run(bf_plan_t p, const int8_t* x, float* out, void* stream) {
     L.xcd_remap = 1;
     const int64_t grid = (L.total_units + 7) / 8 * 8;
     if (grid > 0x7FFFFFFF) return BF_ERR_UNSUPPORTED;
-    hipError_t e = bf::launch_beamform(p->prec, p->mode, p->vec16, p->in4, p->tile, L, (int)grid,
-                                       lds_bytes(p->prec, p->Kpad, p->tile.nbt),
-                                       reinterpret_cast<hipStream_t>(stream));
+    e = bf::launch_beamform(p->prec, p->mode, p->vec16, p->in4, p->tile, L, (int)grid,
+                            lds_bytes(p->prec, p->Kpad, p->tile.nbt), s);
+    if (e == hipSuccess) e = mark_used(p, s);
     return from_hip(e);
   } catch (...) {
     return BF_ERR_HIP;
@@ -652,7 +741,7 @@ int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n) {
     if (n > bf::kMaxProbs) return BF_ERR_UNSUPPORTED;
     for (int i = 0; i < n; ++i) {
       if (!plans[i]) return BF_ERR_INVALID_ARG;
-      if (!plans[i]->weights_set) return BF_ERR_STATE;
+      if (!plans[i]->weights_set && !plans[i]->refresh_pending) return BF_ERR_STATE;
       const bf_plan_s* a = plans[0];
       const bf_plan_s* b = plans[i];
       if (b->cx || b->prec != a->prec || b->mode != a->mode || b->vec16 != a->vec16 ||
@@ -678,6 +767,11 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
   try {
     if (!bt || !x || !out) return BF_ERR_INVALID_ARG;
     const int n = (int)bt->plans.size();
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (int i = 0; i < n; ++i) {
+      hipError_t e = take_refresh(bt->plans[i], s);
+      if (e != hipSuccess) return from_hip(e);
+    }
     Launch L;
     size_t lds = 0;
     Tile common{4, 1, 1, 0};
@@ -687,7 +781,6 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
     const bf_plan_s* p0 = bt->plans[0];
     const bool multi = p0->vec16;
     int per_cu = lds <= 80 * 1024 ? 2 : 1;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
     if (multi) {
       int occ = 0;
@@ -704,6 +797,7 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
                 : bf::launch_beamform(p0->prec, p0->mode, p0->vec16, p0->in4, common, L,
                                       (int)grid, lds, s);
     }
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = mark_used(bt->plans[i], s);
     return from_hip(e);
   } catch (...) {
     return BF_ERR_HIP;
@@ -780,8 +874,10 @@ int bf_table_set(bf_table_t t, const bf_plan_t* plans, const int8_t* const* x, f
     for (int i = 0; i < n; ++i) {
       const bf_plan_s* p = plans[i];
       if (!p) return BF_ERR_INVALID_ARG;
-      if (p->cx || p->N != t->N || p->I != t->I || p->prec != t->prec || p->in4 != t->in4 ||
-          p->device != t->device)
+      // a table's runs are not tracked per plan, so plans refreshed with
+      // bf_set_weights_async (two weight buffers) are not accepted
+      if (p->cx || p->w_alt || p->N != t->N || p->I != t->I || p->prec != t->prec ||
+          p->in4 != t->in4 || p->device != t->device)
         return BF_ERR_UNSUPPORTED;
     }
     Launch L;

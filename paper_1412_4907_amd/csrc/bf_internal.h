@@ -95,9 +95,10 @@ hipError_t launch_beamform_multi(int prec, int mode, bool in4, const Launch& L,
                                  const Launch* table, int grid, size_t lds_bytes,
                                  hipStream_t stream, int* occupancy);
 
+// mask: device [N], 0 drops an antenna (every weight of it is zero).
 hipError_t launch_weights_geom(int prec, const double* pos, const double* dir,
-                               const double* freq, int N, int C, int B, int Bpad, int Kpad,
-                               void* w, hipStream_t stream);
+                               const double* freq, const double* mask, int N, int C, int B,
+                               int Bpad, int Kpad, void* w, hipStream_t stream);
 hipError_t launch_weights_raw(int prec, const double* wraw, int N, int C, int B, int Bpad,
                               int Kpad, void* w, hipStream_t stream);
 hipError_t launch_queue_reset(int32_t* q, hipStream_t stream);

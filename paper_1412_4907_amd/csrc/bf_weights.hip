@@ -87,10 +87,12 @@ __device__ __forceinline__ void put(void* w, int64_t c, int b, int n, int Bpad, 
   row[Kpad + 2 * n + 1] = Store<PREC>::cvt(wr);
 }
 
-// One thread per (c, b < Bpad, n < Kpad/2).
+// One thread per (c, b < Bpad, n < Kpad/2).  mask[n] == 0 drops antenna n
+// (zero weight column: a sub-array beam).
 template <int PREC>
 __global__ void weights_geom_kernel(const double* __restrict__ pos, const double* __restrict__ dir,
-                                    const double* __restrict__ freq, int N, int C, int B,
+                                    const double* __restrict__ freq,
+                                    const double* __restrict__ mask, int N, int C, int B,
                                     int Bpad, int Kpad, void* w) {
   const int half = Kpad / 2;
   const int64_t total = (int64_t)C * Bpad * half;
@@ -101,7 +103,7 @@ __global__ void weights_geom_kernel(const double* __restrict__ pos, const double
     const int b = (int)(cb % Bpad);
     const int64_t c = cb / Bpad;
     double wr = 0.0, wi = 0.0;
-    if (n < N && b < B) {
+    if (n < N && b < B && mask[n] != 0.0) {
       const double kr = dir[3 * b] * pos[3 * n] + dir[3 * b + 1] * pos[3 * n + 1] +
                         dir[3 * b + 2] * pos[3 * n + 2];        // metres
       const double cyc = freq[c] * kr / kC0;                    // phase in cycles
@@ -160,14 +162,17 @@ static hipError_t launch(K kern, int grid, int block, hipStream_t s, A... a) {
 }
 
 hipError_t launch_weights_geom(int prec, const double* pos, const double* dir, const double* freq,
-                               int N, int C, int B, int Bpad, int Kpad, void* w,
-                               hipStream_t s) {
+                               const double* mask, int N, int C, int B, int Bpad, int Kpad,
+                               void* w, hipStream_t s) {
   const int grid = grid_for((int64_t)C * Bpad * (Kpad / 2));
   if (prec == 0)
-    return launch(weights_geom_kernel<0>, grid, 256, s, pos, dir, freq, N, C, B, Bpad, Kpad, w);
+    return launch(weights_geom_kernel<0>, grid, 256, s, pos, dir, freq, mask, N, C, B, Bpad, Kpad,
+                  w);
   if (prec == 1)
-    return launch(weights_geom_kernel<1>, grid, 256, s, pos, dir, freq, N, C, B, Bpad, Kpad, w);
-  return launch(weights_geom_kernel<2>, grid, 256, s, pos, dir, freq, N, C, B, Bpad, Kpad, w);
+    return launch(weights_geom_kernel<1>, grid, 256, s, pos, dir, freq, mask, N, C, B, Bpad, Kpad,
+                  w);
+  return launch(weights_geom_kernel<2>, grid, 256, s, pos, dir, freq, mask, N, C, B, Bpad, Kpad,
+                w);
 }
 
 hipError_t launch_weights_raw(int prec, const double* wraw, int N, int C, int B, int Bpad,
