@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--output", default="power", choices=["power", "complex"],
                     help="detected integrated power, or complex FP16 beams (integration 1)")
     ap.add_argument("--workload", default="paper",
-                    choices=["paper", "small", "precision", "serve", "batch"])
+                    choices=["paper", "small", "precision", "serve", "batch", "tracking"])
     ap.add_argument("--blocks", type=int, default=200, help="serve: blocks to stream")
     ap.add_argument("--pace", type=float, default=10.0,
                     help="serve: replay speed-up over real time for the latency run "
@@ -317,6 +317,77 @@ def serve_bench(a, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def tracking_bench(a, torch, dev):
+    """Tracking beams: a 512-beam set on the serving array (N=256, 1024
+    channels x 8192 samples, I=64) whose pointing changes every block.  Per
+    block time with static weights, with the refresh enqueued on the run
+    stream before each block, and with the refresh generated on a side stream
+    (bf_set_weights_async) while the previous block runs."""
+    from paper_1412_4907_amd import bf, synth, tune
+    blk = synth.serve_block(0)
+    B, steps = 512, max(a.steps, 8)
+    g = synth.rng("serve", "tracking")
+    base = synth.random_dirs(B, g, 25.0)
+
+    def pointing(k):
+        ang = np.deg2rad(0.05 * k)
+        rot = np.array([[np.cos(ang), -np.sin(ang), 0], [np.sin(ang), np.cos(ang), 0], [0, 0, 1]])
+        d = base @ rot.T
+        return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+    x = torch.from_numpy(blk.voltages(workers=16)).to(dev)
+    plan = bf.Plan(blk.n_ant, blk.n_chan, B, blk.n_samples, blk.integration, precision=a.precision)
+    p = torch.empty(plan.p_shape, dtype=plan.p_dtype, device=dev)
+    run_s, side_s = torch.cuda.Stream(), torch.cuda.Stream()
+    plan.set_weights(blk.pos, pointing(0), blk.freqs, stream=run_s)
+    if tune.apply_cached(plan) is None:
+        with torch.cuda.stream(run_s):
+            tune.tune(plan, x, p, reps=3)
+
+    def leg(mode):
+        for k in range(a.warmup):
+            plan.run(x, p, stream=run_s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(run_s)
+        for k in range(steps):
+            if mode == "sync":
+                plan.set_weights(blk.pos, pointing(k + 1), blk.freqs, stream=run_s)
+            elif mode == "async":
+                plan.set_weights_async(blk.pos, pointing(k + 1), blk.freqs, stream=side_s)
+            plan.run(x, p, stream=run_s)
+        e1.record(run_s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    static = leg("static")
+    sync = leg("sync")
+    asyn = leg("async")
+    # the weight generation alone
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(run_s)
+    for k in range(steps):
+        plan.set_weights(blk.pos, pointing(k), blk.freqs, stream=run_s)
+    e1.record(run_s)
+    torch.cuda.synchronize()
+    gen = e0.elapsed_time(e1) / steps
+    flops = 8.0 * blk.n_chan * B * blk.n_samples * blk.n_ant
+    period = blk.n_samples / (16e6 / 1024)
+    out = {"metric": "tracking beams: block time with per-block weight refresh", "value":
+           round(flops / (asyn * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": steps,
+           "warmup": a.warmup, "ms_per_step": round(asyn, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[a.precision], "data": "synthetic",
+           "config": {"workload": f"tracking: N={blk.n_ant} (16x16 grid), C={blk.n_chan}, B={B}, "
+                                  f"T={blk.n_samples}, I={blk.integration}, new pointing per block",
+                      "precision": a.precision, "tile": list(plan.tile())},
+           "static_ms": round(static, 4), "sync_refresh_ms": round(sync, 4),
+           "async_refresh_ms": round(asyn, 4), "weight_generation_ms": round(gen, 4),
+           "hidden_fraction": round((sync - asyn) / max(sync - static, 1e-9), 3),
+           "real_time_factor": round(period / (asyn * 1e-3), 1)}
+    plan.destroy()
+    print(json.dumps(out), flush=True)
+
+
 def batch_bench(a, torch, dev):
     """Batching form: the 12 seeded beam sets of uneven N, C, B, T in one
     persistent launch (tiles from the autotuner cache or each set's default)."""
@@ -402,6 +473,8 @@ def main():
         return serve_bench(a, torch, dev)
     if a.workload == "batch":
         return batch_bench(a, torch, dev)
+    if a.workload == "tracking":
+        return tracking_bench(a, torch, dev)
     w = workload(a.workload)
     if a.input_bits == 4:
         from paper_1412_4907_amd import synth

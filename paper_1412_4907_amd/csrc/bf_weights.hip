@@ -75,67 +75,77 @@ template <> struct Store<2> {
   static __device__ T cvt(double v) { return (uint16_t)round_f64<7, 8>(v); }
 };
 
-// Writes the four operand entries of (c, b, n) from an FP64 weight.
+// Operand entries (2n, 2n+1) of the re-row and the im-row of beam b of
+// channel c: [Re W, -Im W] and [Im W, Re W], each pair one store.
 template <int PREC>
-__device__ __forceinline__ void put(void* w, int64_t c, int b, int n, int Bpad, int Kpad,
-                                    double wr, double wi) {
+__device__ __forceinline__ void put(void* w, int64_t row, int n, int Kpad, double wr, double wi) {
   using T = typename Store<PREC>::T;
-  T* row = reinterpret_cast<T*>(w) + (((int64_t)c * Bpad + b) * 2) * Kpad;
-  row[2 * n] = Store<PREC>::cvt(wr);
-  row[2 * n + 1] = Store<PREC>::cvt(-wi);
-  row[Kpad + 2 * n] = Store<PREC>::cvt(wi);
-  row[Kpad + 2 * n + 1] = Store<PREC>::cvt(wr);
+  T* r0 = reinterpret_cast<T*>(w) + row * 2 * Kpad;
+  if constexpr (PREC == 0) {
+    reinterpret_cast<float2*>(r0)[n] = float2{Store<0>::cvt(wr), Store<0>::cvt(-wi)};
+    reinterpret_cast<float2*>(r0 + Kpad)[n] = float2{Store<0>::cvt(wi), Store<0>::cvt(wr)};
+  } else {
+    const uint32_t re = Store<PREC>::cvt(wr), nim = Store<PREC>::cvt(-wi),
+                   im = Store<PREC>::cvt(wi);
+    reinterpret_cast<uint32_t*>(r0)[n] = re | (nim << 16);
+    reinterpret_cast<uint32_t*>(r0 + Kpad)[n] = im | (re << 16);
+  }
 }
 
-// One thread per (c, b < Bpad, n < Kpad/2).  mask[n] == 0 drops antenna n
-// (zero weight column: a sub-array beam).
+// One workgroup per operand row (c, b < Bpad) at a time, its threads over
+// the antennas n < Kpad/2 (padding written as zeros).  mask[n] == 0 drops
+// antenna n (zero weight column: a sub-array beam).
 template <int PREC>
-__global__ void weights_geom_kernel(const double* __restrict__ pos, const double* __restrict__ dir,
-                                    const double* __restrict__ freq,
-                                    const double* __restrict__ mask, int N, int C, int B,
-                                    int Bpad, int Kpad, void* w) {
+__global__ void __launch_bounds__(64) weights_geom_kernel(
+    const double* __restrict__ pos, const double* __restrict__ dir,
+    const double* __restrict__ freq, const double* __restrict__ mask, int N, int C, int B,
+    int Bpad, int Kpad, void* w) {
   const int half = Kpad / 2;
-  const int64_t total = (int64_t)C * Bpad * half;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int n = (int)(i % half);
-    const int64_t cb = i / half;
-    const int b = (int)(cb % Bpad);
-    const int64_t c = cb / Bpad;
-    double wr = 0.0, wi = 0.0;
-    if (n < N && b < B && mask[n] != 0.0) {
-      const double kr = dir[3 * b] * pos[3 * n] + dir[3 * b + 1] * pos[3 * n + 1] +
-                        dir[3 * b + 2] * pos[3 * n + 2];        // metres
-      const double cyc = freq[c] * kr / kC0;                    // phase in cycles
-      const double frac = cyc - rint(cyc);                      // exact, |frac| <= 1/2
-      double sn, cs;
-      sincospi(2.0 * frac, &sn, &cs);
-      wr = cs;   // exp(-i phi) = cos(phi) - i sin(phi)
-      wi = -sn;
+  const int64_t rows = (int64_t)C * Bpad;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int b = (int)(row % Bpad);
+    const int64_t c = row / Bpad;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    if (b < B) {
+      d0 = dir[3 * b];
+      d1 = dir[3 * b + 1];
+      d2 = dir[3 * b + 2];
     }
-    put<PREC>(w, c, b, n, Bpad, Kpad, wr, wi);
+    for (int n = threadIdx.x; n < half; n += blockDim.x) {
+      double wr = 0.0, wi = 0.0;
+      if (n < N && b < B && mask[n] != 0.0) {
+        const double kr = d0 * pos[3 * n] + d1 * pos[3 * n + 1] + d2 * pos[3 * n + 2];  // m
+        const double cyc = freq[c] * kr / kC0;                    // phase in cycles
+        const double frac = cyc - rint(cyc);                      // exact, |frac| <= 1/2
+        double sn, cs;
+        sincospi(2.0 * frac, &sn, &cs);
+        wr = cs;   // exp(-i phi) = cos(phi) - i sin(phi)
+        wi = -sn;
+      }
+      put<PREC>(w, row, n, Kpad, wr, wi);
+    }
   }
 }
 
 // Raw complex weights [C][B][N][2] (device copy) -> operand layout.
 template <int PREC>
-__global__ void weights_raw_kernel(const double* __restrict__ wraw, int N, int C, int B, int Bpad,
-                                   int Kpad, void* w) {
+__global__ void __launch_bounds__(64) weights_raw_kernel(const double* __restrict__ wraw, int N,
+                                                         int C, int B, int Bpad, int Kpad,
+                                                         void* w) {
   const int half = Kpad / 2;
-  const int64_t total = (int64_t)C * Bpad * half;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int n = (int)(i % half);
-    const int64_t cb = i / half;
-    const int b = (int)(cb % Bpad);
-    const int64_t c = cb / Bpad;
-    double wr = 0.0, wi = 0.0;
-    if (n < N && b < B) {
-      const double* src = wraw + ((c * B + b) * N + n) * 2;
-      wr = src[0];
-      wi = src[1];
+  const int64_t rows = (int64_t)C * Bpad;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int b = (int)(row % Bpad);
+    const int64_t c = row / Bpad;
+    for (int n = threadIdx.x; n < half; n += blockDim.x) {
+      double wr = 0.0, wi = 0.0;
+      if (n < N && b < B) {
+        const double* src = wraw + ((c * B + b) * N + n) * 2;
+        wr = src[0];
+        wi = src[1];
+      }
+      put<PREC>(w, row, n, Kpad, wr, wi);
     }
-    put<PREC>(w, c, b, n, Bpad, Kpad, wr, wi);
   }
 }
 
@@ -150,9 +160,9 @@ __global__ void __launch_bounds__(kThreads) table_store_kernel(const Launch L, L
   for (int i = threadIdx.x; i < (int)(sizeof(Launch) / 4); i += kThreads) d[i] = src[i];
 }
 
-static int grid_for(int64_t total) {
-  int64_t g = (total + 255) / 256;
-  return (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+// One workgroup per operand row, at most 2^20 of them (each then loops).
+static int grid_rows(int64_t rows) {
+  return (int)(rows < (1 << 20) ? (rows > 0 ? rows : 1) : (1 << 20));
 }
 
 template <typename K, typename... A>
@@ -164,23 +174,23 @@ static hipError_t launch(K kern, int grid, int block, hipStream_t s, A... a) {
 hipError_t launch_weights_geom(int prec, const double* pos, const double* dir, const double* freq,
                                const double* mask, int N, int C, int B, int Bpad, int Kpad,
                                void* w, hipStream_t s) {
-  const int grid = grid_for((int64_t)C * Bpad * (Kpad / 2));
+  const int grid = grid_rows((int64_t)C * Bpad);
   if (prec == 0)
-    return launch(weights_geom_kernel<0>, grid, 256, s, pos, dir, freq, mask, N, C, B, Bpad, Kpad,
+    return launch(weights_geom_kernel<0>, grid, 64, s, pos, dir, freq, mask, N, C, B, Bpad, Kpad,
                   w);
   if (prec == 1)
-    return launch(weights_geom_kernel<1>, grid, 256, s, pos, dir, freq, mask, N, C, B, Bpad, Kpad,
+    return launch(weights_geom_kernel<1>, grid, 64, s, pos, dir, freq, mask, N, C, B, Bpad, Kpad,
                   w);
-  return launch(weights_geom_kernel<2>, grid, 256, s, pos, dir, freq, mask, N, C, B, Bpad, Kpad,
+  return launch(weights_geom_kernel<2>, grid, 64, s, pos, dir, freq, mask, N, C, B, Bpad, Kpad,
                 w);
 }
 
 hipError_t launch_weights_raw(int prec, const double* wraw, int N, int C, int B, int Bpad,
                               int Kpad, void* w, hipStream_t s) {
-  const int grid = grid_for((int64_t)C * Bpad * (Kpad / 2));
-  if (prec == 0) return launch(weights_raw_kernel<0>, grid, 256, s, wraw, N, C, B, Bpad, Kpad, w);
-  if (prec == 1) return launch(weights_raw_kernel<1>, grid, 256, s, wraw, N, C, B, Bpad, Kpad, w);
-  return launch(weights_raw_kernel<2>, grid, 256, s, wraw, N, C, B, Bpad, Kpad, w);
+  const int grid = grid_rows((int64_t)C * Bpad);
+  if (prec == 0) return launch(weights_raw_kernel<0>, grid, 64, s, wraw, N, C, B, Bpad, Kpad, w);
+  if (prec == 1) return launch(weights_raw_kernel<1>, grid, 64, s, wraw, N, C, B, Bpad, Kpad, w);
+  return launch(weights_raw_kernel<2>, grid, 64, s, wraw, N, C, B, Bpad, Kpad, w);
 }
 
 hipError_t launch_queue_reset(int32_t* q, hipStream_t s) {
