@@ -166,6 +166,27 @@ int bf_set_weights_async(bf_plan_t plan, const double* ant_xyz_m, const double* 
 int bf_plan_set_antenna_mask(bf_plan_t plan, const uint8_t* mask);
 
 /*
+ * Beam-pattern (array-factor) map of the plan's weights (Sec. 3.1 simulates
+ * the BEST-2 beam pattern from the beamforming coefficients over a sky grid;
+ * Eq. 1): for every channel c, beam b and grid direction k_g,
+ *     P[c][b][g] = | sum_n W[c][b][n] exp(+i 2 pi f_c (k_g . r_n) / c0) |^2,
+ * the power the plan's beam b collects from a unit plane wave arriving from
+ * k_g (N^2 on the beam's own direction for unit weights), computed with the
+ * plan's rounded weights (so the map shows the precision form's real beam)
+ * and the antenna mask they carry.  ant_xyz_m host [N][3], chan_freq_hz
+ * host [C] (as for bf_set_weights), grid_dir host [n_dirs][3] unit vectors,
+ * 1 <= n_dirs <= 2^24; p_dev device float [C][B][n_dirs], 4-byte aligned.
+ * The steering phase is formed in FP64 and reduced modulo one cycle; sin/cos
+ * and the sums are FP32.  A validation tool, not a hot path: it allocates a
+ * device buffer for the geometry and returns after the map is complete.
+ * Errors: BF_ERR_INVALID_ARG (null pointer, size, misaligned output,
+ * non-finite value, non-unit direction, non-positive frequency),
+ * BF_ERR_STATE (no weights), BF_ERR_OOM, BF_ERR_HIP.
+ */
+int bf_beam_pattern(bf_plan_t plan, const double* ant_xyz_m, const double* chan_freq_hz,
+                    const double* grid_dir, int32_t n_dirs, float* p_dev, void* stream);
+
+/*
  * Load arbitrary complex weights (host [C][B][N][2] double, re/im), each
  * component rounded once to the storage precision.  Synchronous (returns
  * after the device copy is complete).  Used for DFT/integer-weight tests

@@ -13,6 +13,9 @@ The arithmetic lives in ``bf_oracle.c`` (plain FP64 loops, OpenMP over
   summed over non-overlapping windows of I samples.  ``x`` is int8
   [C][T][N][2] or complex128 [C][T][N] (unquantised input for the pins).
 * ``beams(w, x)``                -> complex128 [C][B][T] before detection.
+* ``steering(pos, dirs, freqs)``  -> complex128 [C][G][N]: a unit plane wave
+  from each direction as the antennas receive it, exp(+i 2 pi f_c (k_g . r_n)
+  / c0) (Sec. 1); |beams(w, steering)|^2 is the beam-pattern map (Sec. 3.1).
 * ``unpack4(x4)``                -> int8 [...][2]: 4-bit complex samples (one
   byte each, Sec. 2.1: two 4-bit two's complement components per antenna
   sample) widened to (re, im); the real part is the high nibble.
@@ -155,3 +158,18 @@ def unpack4(x4) -> np.ndarray:
     re = np.where(hi >= 8, hi - 16, hi)
     im = np.where(lo >= 8, lo - 16, lo)
     return np.stack([re, im], axis=-1).astype(np.int8)
+
+
+C0 = 299_792_458.0  # m/s
+
+
+def steering(pos, dirs, freqs) -> np.ndarray:
+    """Unit plane waves: [C][G][N] complex128, entry (c, g, n) =
+    exp(+i 2 pi f_c (k_g . r_n) / c0) -- the phase a wavefront from k_g
+    carries at antenna n relative to the origin (Sec. 1, the delay picture
+    behind Eq. 1), evaluated directly in FP64."""
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    dirs = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+    freqs = np.asarray(freqs, dtype=np.float64).reshape(-1)
+    delay = (dirs @ pos.T) / C0                     # [G][N] seconds
+    return np.exp(2j * np.pi * freqs[:, None, None] * delay[None])

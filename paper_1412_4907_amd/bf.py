@@ -27,7 +27,7 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = 0, -1, -2, -
 # every entry point declared in include/bf.h
 EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_plan_create",
            "bf_plan_create_ex", "bf_set_weights", "bf_set_weights_async",
-           "bf_plan_set_antenna_mask", "bf_set_weights_raw", "bf_get_weights",
+           "bf_plan_set_antenna_mask", "bf_beam_pattern", "bf_set_weights_raw", "bf_get_weights",
            "bf_run", "bf_plan_info", "bf_plan_set_tile", "bf_plan_set_output_scale",
            "bf_plan_tile_candidates",
            "bf_plan_destroy", "bf_batch_create", "bf_batch_tile_candidates", "bf_batch_run",
@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         L.bf_set_weights.argtypes = [P, P, P, P, P]
         L.bf_set_weights_async.argtypes = [P, P, P, P, P]
         L.bf_plan_set_antenna_mask.argtypes = [P, P]
+        L.bf_beam_pattern.argtypes = [P, P, P, P, i32, P, P]
         L.bf_set_weights_raw.argtypes = [P, P, P]
         L.bf_get_weights.argtypes = [P, P, P]
         L.bf_run.argtypes = [P, P, P, P]
@@ -213,6 +214,24 @@ class Plan:
         _check(lib().bf_set_weights_async(self.handle, pos.ctypes.data, dirs.ctypes.data,
                                           freqs.ctypes.data, _stream_ptr(stream)),
                "bf_set_weights_async")
+
+    def beam_pattern(self, pos, freqs, grid_dirs, out=None, stream=None):
+        """Power of every beam for a unit plane wave from each grid direction:
+        float32 [C][B][G] device tensor (``bf_beam_pattern``)."""
+        import torch
+        pos = _host_f64(pos, (self.N, 3))
+        freqs = _host_f64(freqs, (self.C,))
+        gd = np.ascontiguousarray(grid_dirs, dtype=np.float64).reshape(-1, 3)
+        G = gd.shape[0]
+        if out is None:
+            out = torch.empty((self.C, self.B, G), dtype=torch.float32, device="cuda")
+        if out.dtype != torch.float32 or tuple(out.shape) != (self.C, self.B, G) or \
+                not out.is_cuda or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float32 device tensor [{self.C}][{self.B}][{G}]")
+        _check(lib().bf_beam_pattern(self.handle, pos.ctypes.data, freqs.ctypes.data,
+                                     gd.ctypes.data, G, out.data_ptr(), _stream_ptr(stream)),
+               "bf_beam_pattern")
+        return out
 
     def set_antenna_mask(self, mask=None) -> None:
         """Antennas used by weights generated from now on (None: all)."""

@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libbf.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["bf_api.cpp", "bf_weights.hip", "bf_beamform_f32.hip", "bf_beamform_f16.hip",
+SOURCES = ["bf_api.cpp", "bf_weights.hip", "bf_pattern.hip", "bf_beamform_f32.hip", "bf_beamform_f16.hip",
            "bf_beamform_bf16.hip", "bf_beamform_f32_in4.hip", "bf_beamform_f16_in4.hip",
            "bf_beamform_bf16_in4.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -552,6 +552,49 @@ int bf_set_weights_async(bf_plan_t p, const double* pos, const double* dir, cons
   }
 }
 
+int bf_beam_pattern(bf_plan_t p, const double* pos, const double* freq, const double* grid_dir,
+                    int32_t n_dirs, float* p_dev, void* stream) {
+  try {
+    if (!p || !pos || !freq || !grid_dir || !p_dev || n_dirs < 1 || n_dirs > (1 << 24) ||
+        ((uintptr_t)p_dev & 3u) != 0)
+      return BF_ERR_INVALID_ARG;
+    if (!p->weights_set && !p->refresh_pending) return BF_ERR_STATE;
+    for (int64_t i = 0; i < 3 * (int64_t)p->N; ++i)
+      if (!std::isfinite(pos[i])) return BF_ERR_INVALID_ARG;
+    for (int c = 0; c < p->C; ++c)
+      if (!std::isfinite(freq[c]) || !(freq[c] > 0.0)) return BF_ERR_INVALID_ARG;
+    for (int g = 0; g < n_dirs; ++g) {
+      const double* d = grid_dir + 3 * (int64_t)g;
+      if (!std::isfinite(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2]))
+        return BF_ERR_INVALID_ARG;
+      if (std::fabs(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) > 1e-9)
+        return BF_ERR_INVALID_ARG;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = take_refresh(p, s);
+    if (e != hipSuccess) return from_hip(e);
+    const size_t nd = (size_t)3 * p->N + (size_t)p->C + (size_t)3 * n_dirs;
+    std::vector<double> h(nd);
+    std::memcpy(h.data(), pos, sizeof(double) * 3 * p->N);
+    std::memcpy(h.data() + 3 * p->N, freq, sizeof(double) * p->C);
+    std::memcpy(h.data() + 3 * p->N + p->C, grid_dir, sizeof(double) * 3 * (size_t)n_dirs);
+    double* d = nullptr;
+    e = hipMalloc(&d, nd * sizeof(double));
+    if (e != hipSuccess) return from_hip(e);
+    e = hipMemcpyAsync(d, h.data(), nd * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = bf::launch_beam_pattern(p->prec, p->w_dev, d, d + 3 * p->N + p->C, d + 3 * p->N,
+                                  p->N, p->C, p->B, p->Bpad, p->Kpad, n_dirs, p_dev, s);
+    if (e == hipSuccess) e = mark_used(p, s);
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return from_hip(e);
+    return from_hip(e2);
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
 int bf_plan_set_antenna_mask(bf_plan_t p, const uint8_t* mask) {
   if (!p) return BF_ERR_INVALID_ARG;
   for (int n = 0; n < p->N; ++n) p->mask[n] = (!mask || mask[n]) ? 1.0 : 0.0;

@@ -95,6 +95,12 @@ hipError_t launch_beamform_multi(int prec, int mode, bool in4, const Launch& L,
                                  const Launch* table, int grid, size_t lds_bytes,
                                  hipStream_t stream, int* occupancy);
 
+// Beam-pattern map: P[c][b][g] over G grid directions (device pos [N][3],
+// gdir [G][3], freq [C]; weights in the plan's operand layout).
+hipError_t launch_beam_pattern(int prec, const void* w, const double* pos, const double* gdir,
+                               const double* freq, int N, int C, int B, int Bpad, int Kpad, int G,
+                               float* out, hipStream_t stream);
+
 // mask: device [N], 0 drops an antenna (every weight of it is zero).
 hipError_t launch_weights_geom(int prec, const double* pos, const double* dir,
                                const double* freq, const double* mask, int N, int C, int B,

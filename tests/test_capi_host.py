@@ -55,6 +55,7 @@ def test_validation_before_any_device_call():
     assert L.bf_plan_set_output_scale(None, 1.0) == bf.ERR_INVALID_ARG
     assert L.bf_set_weights_async(None, None, None, None, None) == bf.ERR_INVALID_ARG
     assert L.bf_plan_set_antenna_mask(None, None) == bf.ERR_INVALID_ARG
+    assert L.bf_beam_pattern(None, None, None, None, 1, None, None) == bf.ERR_INVALID_ARG
     # 4-bit rows are read 8 antennas at a time
     assert L.bf_plan_create_ex(ctypes.byref(h), 12, 1, 1, 16, 1, 0, bf.INPUT_4BIT) == \
         bf.ERR_UNSUPPORTED

@@ -355,3 +355,38 @@ def test_beams_on_beam_plane_wave_and_power():
     P = oracle.beamform(W, x, 4)
     np.testing.assert_allclose(P, (np.abs(Bm) ** 2).reshape(2, 2, T // 4, 4).sum(-1),
                                rtol=1e-12)
+
+
+# --- steering vectors and the beam-pattern map (Sec. 1, Sec. 3.1) -----------
+
+def test_steering_special_values_and_on_beam():
+    f = 400e6
+    lam = C0 / f
+    k = np.array([[0.0, 0.0, 1.0]])
+    pos = np.array([[0, 0, 0], [0, 0, lam / 4], [0, 0, lam / 2], [7.0, -3.0, 0]], dtype=float)
+    s = oracle.steering(pos, k, [f])[0, 0]
+    # a wave from k reaches an antenna a quarter wavelength toward k earlier: +i
+    np.testing.assert_allclose(s, [1, 1j, -1, 1], atol=1e-12)
+    w = synth.paper()
+    S = oracle.steering(w.pos, w.dirs[:5], w.freqs[:3])
+    W = oracle.weights(w.pos, w.dirs[:5], w.freqs[:3])
+    Bm = oracle.beams(W, S)                        # [C][B][G]
+    np.testing.assert_allclose(np.diagonal(Bm, axis1=1, axis2=2), 32.0, atol=1e-10)
+
+
+def test_pattern_line_array_dirichlet():
+    """Pattern of a uniform line array steered to theta_b, seen from theta_g:
+    |sum_n exp(i 2 pi (d / lambda) (sin theta_g - sin theta_b) n)|^2 =
+    sin^2(N x) / sin^2(x), x = pi (d / lambda) (sin theta_g - sin theta_b)."""
+    N, d, f = 24, 9.0, 407e6
+    pos = synth.line_positions(N, d)
+    tb = np.array([0.0, 12.5])
+    tg = np.linspace(-40.0, 40.0, 161)
+    W = oracle.weights(pos, synth.dir_from_xz_angle(tb), [f])
+    P = np.abs(oracle.beams(W, oracle.steering(pos, synth.dir_from_xz_angle(tg), [f]))[0]) ** 2
+    lam = C0 / f
+    for i, b in enumerate(tb):
+        x = np.pi * d / lam * (np.sin(np.deg2rad(tg)) - np.sin(np.deg2rad(b)))
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ref = np.where(np.abs(np.sin(x)) < 1e-12, N * N, np.sin(N * x) ** 2 / np.sin(x) ** 2)
+        np.testing.assert_allclose(P[i], ref, rtol=1e-9, atol=1e-9 * N * N)
