@@ -261,6 +261,8 @@ def serve_bench(a, torch, dev):
     ring = []
     for k in range(2):
         blk = synth.serve_block(k)
+        if a.input_bits == 4:
+            blk = synth.four_bit(blk)
         ring.append(torch.from_numpy(blk.voltages(workers=16)).to(dev))
     gen_s = time.perf_counter() - t0
     fp = lambda r: serve.footprint_bytes(r.n_beams, 256, C, T, I, prec)  # noqa: E731
@@ -270,7 +272,8 @@ def serve_bench(a, torch, dev):
            "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
            "config": {"workload": "serve: N=256 (16x16 grid, 10 m), C=1024, T=8192 per block "
                                   "(524.288 ms), I=64, Poisson beam-set requests 64..2048 beams",
-                      "precision": prec, "hbm_budget_gb": a.serve_budget_gb,
+                      "precision": prec, "input_bits": a.input_bits,
+                      "hbm_budget_gb": a.serve_budget_gb,
                       "ring_slots": len(ring), "blocks": a.blocks,
                       "paced_arrivals": f"seeded Poisson, mean gap {period / a.pace * 1e3:.3f} ms "
                                         f"({a.pace:g}x real time)"}}
@@ -278,7 +281,8 @@ def serve_bench(a, torch, dev):
     def run(reqs_spec, n_blocks, arrivals=None, host_blocks=None):
         reqs = [serve.Request(i, d, lifetime=life, arrival_block=arr_b)
                 for i, (arr_b, nb, life, d) in enumerate(reqs_spec)]
-        ex = serve.GpuExecutor(pos, freqs, T, I, prec, ring=ring, host_blocks=host_blocks)
+        ex = serve.GpuExecutor(pos, freqs, T, I, prec, ring=ring, host_blocks=host_blocks,
+                               input_bits=a.input_bits)
         sch = serve.Scheduler(budget, fp)
         recs = serve.serve(ex, sch, reqs, n_blocks=n_blocks, block_period_s=period,
                            arrivals=arrivals)

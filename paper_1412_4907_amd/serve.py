@@ -158,7 +158,7 @@ class GpuExecutor:
 
     def __init__(self, pos: np.ndarray, freqs: np.ndarray, n_samples: int, integration: int,
                  precision: str = "fp16", ring: Sequence = (), use_graphs: bool = True,
-                 host_blocks: Optional[Sequence] = None):
+                 host_blocks: Optional[Sequence] = None, input_bits: int = 8):
         import torch
         from . import bf, tune
         self.torch, self.bf, self.tune = torch, bf, tune
@@ -166,7 +166,8 @@ class GpuExecutor:
         self.N, self.C = pos.shape[0], freqs.shape[0]
         self.T, self.I = n_samples, integration
         self.precision = precision
-        self.ring = list(ring)           # device int8 [C][T][N][2] tensors
+        self.input_bits = input_bits     # 8: int8 [C][T][N][2] blocks; 4: packed uint8 [C][T][N]
+        self.ring = list(ring)           # device voltage blocks
         self.use_graphs = use_graphs
         self.stream = torch.cuda.Stream()
         # PCIe-fed variant: every block is first copied from pinned host memory
@@ -179,7 +180,7 @@ class GpuExecutor:
         self.h2d_bytes = 0
         self.plans: Dict[int, object] = {}
         self.outs: Dict[int, List] = {}
-        self.table = bf.Table(self.N, self.I, precision)
+        self.table = bf.Table(self.N, self.I, precision, input_bits=input_bits)
         self.graph = None
         self.graveyard: List = []
         self.graveyard_outs: List = []
@@ -190,7 +191,8 @@ class GpuExecutor:
 
     def admit(self, r: Request) -> None:
         torch = self.torch
-        plan = self.bf.Plan(self.N, self.C, r.n_beams, self.T, self.I, precision=self.precision)
+        plan = self.bf.Plan(self.N, self.C, r.n_beams, self.T, self.I, precision=self.precision,
+                            input_bits=self.input_bits)
         with torch.cuda.stream(self.stream):
             plan.set_weights(self.pos, r.dirs, self.freqs, stream=self.stream)
             self.outs[r.rid] = [torch.empty((self.C, r.n_beams, self.T // self.I),

@@ -12,14 +12,17 @@ from tests.gpu_util import assert_parity
 pytestmark = pytest.mark.gpu
 
 
-def test_serve_alone_equals_mix(gpu):
+@pytest.mark.parametrize("input_bits", [8, 4])
+def test_serve_alone_equals_mix(gpu, input_bits):
     import torch
-    print("serve mix", flush=True)
+    print(f"serve mix, {input_bits}-bit blocks", flush=True)
     pos = synth.serve_array()
     C, T, I = 16, 2048, 64
     freqs = synth.channel_freqs(C, 400e6, 16e6)
+    sigma = synth.SIGMA4 if input_bits == 4 else synth.SIGMA
     blocks = [synth.Workload(f"b{k}", 2000 + k, 256, C, 0, T, I, pos, np.zeros((0, 3)),
-                             freqs).voltages() for k in range(2)]
+                             freqs, sigma=sigma, input_bits=input_bits).voltages()
+              for k in range(2)]
     ring = [torch.from_numpy(b).to(gpu) for b in blocks]
     g = np.random.default_rng(5)
     reqs = [serve.Request(i, synth.random_dirs(int(nb), g), lifetime=int(life), arrival_block=int(a))
@@ -27,7 +30,7 @@ def test_serve_alone_equals_mix(gpu):
                                                 (16, 1, 3), (48, 3, 3)])]
     fp = lambda r: serve.footprint_bytes(r.n_beams, 256, C, T, I, "fp16")  # noqa: E731
     budget = fp(reqs[0]) + fp(reqs[2]) + fp(reqs[1])  # forces some requests to wait
-    ex = serve.GpuExecutor(pos, freqs, T, I, "fp16", ring=ring)
+    ex = serve.GpuExecutor(pos, freqs, T, I, "fp16", ring=ring, input_bits=input_bits)
     sch = serve.Scheduler(budget, fp)
     snaps = {}
 
@@ -49,7 +52,7 @@ def test_serve_alone_equals_mix(gpu):
     # alone == in the mix, bitwise, for every (request, block)
     solo = {}
     for r in reqs:
-        plan = bf.Plan(256, C, r.n_beams, T, I, precision="fp16")
+        plan = bf.Plan(256, C, r.n_beams, T, I, precision="fp16", input_bits=input_bits)
         plan.set_weights(pos, r.dirs, freqs)
         for slot in range(2):
             p = torch.empty((C, r.n_beams, T // I), device=gpu)
@@ -61,7 +64,8 @@ def test_serve_alone_equals_mix(gpu):
         assert np.array_equal(t.cpu().numpy(), solo[(rid, k % 2)]), (rid, k)
     # and one request against the oracle on two channels
     r = reqs[2]
-    ref = oracle.beamform(oracle.weights(pos, r.dirs, freqs[:2]), blocks[1][:2], I)
+    x1 = oracle.unpack4(blocks[1][:2]) if input_bits == 4 else blocks[1][:2]
+    ref = oracle.beamform(oracle.weights(pos, r.dirs, freqs[:2]), x1, I)
     assert_parity(solo[(r.rid, 1)][:2], ref, 2e-3, "serve fp16 vs oracle")
     ex.close()
     st = serve.summarize(recs, 0.524288)
