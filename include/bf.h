@@ -110,8 +110,13 @@ const char* bf_last_hip_error(void);
  * device weight buffer (C * ceil(B/16)*16 * 2 * K rows, K = 64*ceil(N/32),
  * in the storage precision) on the current device and a small pinned host
  * staging area.  On success *out owns them until bf_plan_destroy.
+ * Every work unit stages its beams' weights for all K = 2N in LDS, which
+ * bounds the antennas this build supports: N <= 1248 for FP16/BF16 and
+ * N <= 608 for FP32 (BF_ERR_UNSUPPORTED above).
  * Errors: BF_ERR_INVALID_ARG (sizes, null out, unknown precision or flags),
- * BF_ERR_OOM, BF_ERR_HIP.  *out is set to NULL on failure.
+ * BF_ERR_UNSUPPORTED (N above the LDS bound, or an unsupported flag
+ * combination such as 4-bit input with N % 8 != 0), BF_ERR_OOM, BF_ERR_HIP.
+ * *out is set to NULL on failure.
  */
 int bf_plan_create(bf_plan_t* out, int32_t n_antennas, int32_t n_channels, int32_t n_beams,
                    int64_t n_samples, int32_t integration);

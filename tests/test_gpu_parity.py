@@ -262,3 +262,26 @@ def test_error_paths(gpu):
         plan.run(x, p)
         torch.cuda.synchronize()
         assert float(p.abs().sum()) == 0.0
+
+
+# --- the largest arrays this build supports -----------------------------------
+# Each work unit keeps its beams' weights for all K = 2N in LDS: N <= 1248 in
+# FP16/BF16 and N <= 608 in FP32; one antenna group (8) more is rejected.
+
+@pytest.mark.parametrize("prec,n_max", [("fp32", 608), ("fp16", 1248), ("bf16", 1248)])
+def test_largest_supported_array(gpu, prec, n_max):
+    print(f"largest array {prec} N={n_max}", flush=True)
+    g = np.random.default_rng(n_max)
+    C, B, T, I = 2, 20, 96, 4
+    pos = synth.disc_positions(n_max, 400.0, g)
+    dirs = synth.random_dirs(B, g)
+    freqs = np.array([401e6, 414e6])
+    x = g.integers(-128, 128, (C, T, n_max, 2)).astype(np.int8)
+    with bf.Plan(n_max, C, B, T, I, precision=prec) as plan:
+        plan.set_weights(pos, dirs, freqs)
+        got = run_plan(plan, x, gpu)
+    ref = oracle.beamform(oracle.weights(pos, dirs, freqs), x, I)
+    assert_parity(got, ref, TOL[prec], f"N={n_max} {prec}")
+    with pytest.raises(bf.BfError) as e:
+        bf.Plan(n_max + 8, C, B, T, I, precision=prec)
+    assert e.value.status == bf.ERR_UNSUPPORTED
