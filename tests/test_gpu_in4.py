@@ -151,3 +151,30 @@ def test_4bit_input_checks(gpu):
         plan.run(x, p)
         torch.cuda.synchronize()
         assert float(p.abs().sum()) == 0.0
+
+
+def test_4bit_accumulate(gpu):
+    """Integration across blocks (BF_ACCUMULATE) with 4-bit input: the second
+    block adds into the first's output, exactly as the int8 plan does."""
+    import torch
+    N, C, B, T, I = 32, 2, 40, 512, 16
+    pos, dirs, freqs, x4a = _case((N, C, B, T, I), 90)
+    x4b = np.random.default_rng(91).integers(0, 256, (C, T, N)).astype(np.uint8)
+    with bf.Plan(N, C, B, T, I, input_bits=4) as a, \
+            bf.Plan(N, C, B, T, I, input_bits=4, accumulate=True) as acc, \
+            bf.Plan(N, C, B, T, I, accumulate=True) as acc8:
+        for p in (a, acc, acc8):
+            p.set_weights(pos, dirs, freqs)
+        p1 = run_plan(a, x4a, gpu)
+        out = torch.from_numpy(p1).to(gpu)
+        acc.run(torch.from_numpy(x4b).to(gpu), out)
+        out8 = torch.from_numpy(p1).to(gpu)
+        acc8.run(torch.from_numpy(oracle.unpack4(x4b)).to(gpu), out8)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        assert np.array_equal(got, out8.cpu().numpy())
+    # window w of the result is window w of block a plus window w of block b
+    W = oracle.weights(pos, dirs, freqs)
+    ra = oracle.beamform(W, oracle.unpack4(x4a), I)
+    rb = oracle.beamform(W, oracle.unpack4(x4b), I)
+    assert_parity(got, ra + rb, 1e-5, "4-bit accumulate")

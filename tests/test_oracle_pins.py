@@ -390,3 +390,28 @@ def test_pattern_line_array_dirichlet():
         with np.errstate(invalid="ignore", divide="ignore"):
             ref = np.where(np.abs(np.sin(x)) < 1e-12, N * N, np.sin(N * x) ** 2 / np.sin(x) ** 2)
         np.testing.assert_allclose(P[i], ref, rtol=1e-9, atol=1e-9 * N * N)
+
+
+def test_unpack4_pins_catch_planted_mistakes():
+    """Plausible slips in a 4-bit decoder — nibbles swapped, nibbles read as
+    unsigned, sign-magnitude instead of two's complement, the sign bit
+    dropped, values left scaled by 16 — each disagree with the worked bytes."""
+    rows = json.load(open(NIBBLES))["samples"]
+    b = np.array([r[0] for r in rows], dtype=np.uint8)
+    want = [[r[1], r[2]] for r in rows]
+
+    def pair(hi, lo):
+        return np.stack([hi, lo], axis=-1).astype(np.int64).tolist()
+
+    hi, lo = (b >> 4).astype(np.int64), (b & 15).astype(np.int64)
+    tc = lambda v: np.where(v >= 8, v - 16, v)  # noqa: E731
+    mutants = {
+        "swapped": pair(tc(lo), tc(hi)),
+        "unsigned": pair(hi, lo),
+        "sign-magnitude": pair(np.where(hi >= 8, -(hi - 8), hi), np.where(lo >= 8, -(lo - 8), lo)),
+        "sign dropped": pair(hi & 7, lo & 7),
+        "scaled by 16": pair(tc(hi) * 16, tc(lo) * 16),
+    }
+    assert oracle.unpack4(b).tolist() == want
+    for name, got in mutants.items():
+        assert got != want, name
