@@ -110,12 +110,13 @@ const char* bf_last_hip_error(void);
  * device weight buffer (C * ceil(B/16)*16 * 2 * K rows, K = 64*ceil(N/32),
  * in the storage precision) on the current device and a small pinned host
  * staging area.  On success *out owns them until bf_plan_destroy.
- * Every work unit stages its beams' weights for all K = 2N in LDS, which
- * bounds the antennas this build supports: N <= 1248 for FP16/BF16 and
- * N <= 608 for FP32 (BF_ERR_UNSUPPORTED above).
+ * Work units stage their beams' weights for all K = 2N in LDS up to
+ * N = 1248 (FP16/BF16) or N = 608 (FP32); larger arrays read the weight
+ * fragments from device memory instead (tile kres = -1, chosen
+ * automatically; slower, and not accepted by the batching and table forms).
  * Errors: BF_ERR_INVALID_ARG (sizes, null out, unknown precision or flags),
- * BF_ERR_UNSUPPORTED (N above the LDS bound, or an unsupported flag
- * combination such as 4-bit input with N % 8 != 0), BF_ERR_OOM, BF_ERR_HIP.
+ * BF_ERR_UNSUPPORTED (an unsupported flag combination such as 4-bit input
+ * with N % 8 != 0), BF_ERR_OOM, BF_ERR_HIP.
  * *out is set to NULL on failure.
  */
 int bf_plan_create(bf_plan_t* out, int32_t n_antennas, int32_t n_channels, int32_t n_beams,
@@ -229,7 +230,8 @@ typedef struct {
   int32_t tile_mt;        /* 16-sample MFMA row tiles per wave step             */
   int32_t tile_nbt;       /* 16-beam tiles per workgroup                        */
   int32_t tile_nbp;       /* 16-beam tiles per accumulator pass                 */
-  int32_t tile_kres;      /* 64-element K chunks held in registers (0: streamed) */
+  int32_t tile_kres;      /* 64-element K chunks held in registers (0: streamed,
+                             -1: streamed, weights read from device memory) */
   int32_t sg_per_wave;    /* 16-window store groups per wave per work unit      */
   int64_t work_units;     /* workgroups of one bf_run                           */
   int64_t weight_bytes;   /* device bytes of the weight buffer                  */
@@ -242,7 +244,9 @@ int bf_plan_info(bf_plan_t plan, bf_plan_info_t* info);
  * Override the plan's tile choice (used by the autotuner): mt row tiles of
  * 16 samples per wave step, nbt 16-beam tiles per workgroup, nbp beam tiles
  * per accumulator pass, kres K chunks of 64 held in registers (0 = streamed
- * K), sg_per_wave 16-window store groups per wave per work unit.  A
+ * K with the unit's weights in LDS, -1 = streamed K with the weights read
+ * from device memory), sg_per_wave 16-window store groups per wave per work
+ * unit.  A
  * combination this build does not compile, or that the plan's K or LDS
  * budget excludes, returns BF_ERR_UNSUPPORTED and leaves the plan unchanged;
  * sg_per_wave * (row tiles per store group) must be a multiple of mt

@@ -85,6 +85,10 @@ size_t lds_bytes(int prec, int Kpad, int nbt) {
   return (size_t)2 * 16 * nbt * ((size_t)Kpad * es_of(prec) + bf::kLdsPad);
 }
 
+// Dynamic LDS of a tile: the unit's weight rows, none when they are read
+// from device memory.
+size_t tile_lds(int prec, int Kpad, Tile t) { return t.kres < 0 ? 0 : lds_bytes(prec, Kpad, t.nbt); }
+
 int mode_of(int32_t I) {
   return I == 1 ? bf::kModeI1 : I == 2 ? bf::kModeI2 : (I % 4 == 0 ? bf::kModeGen4 : bf::kModeGen);
 }
@@ -170,7 +174,7 @@ int64_t units_for(const bf_plan_s* p, Tile t, int32_t sgw) {
 bool tile_ok(const bf_plan_s* p, Tile t) {
   if (!tile_exists(p, t)) return false;
   if (t.kres > 0 && p->Kpad / bf::kChunk > t.kres) return false;
-  return lds_bytes(p->prec, p->Kpad, t.nbt) <= kLdsMax;
+  return tile_lds(p->prec, p->Kpad, t) <= kLdsMax;
 }
 
 // Default tile: the largest beam range whose weight slice fits 80 KB of LDS
@@ -185,7 +189,9 @@ void choose_tile(bf_plan_s* p) {
   int nbt = 8;
   while (nbt > 1 && (lds_bytes(p->prec, p->Kpad, nbt) > 80 * 1024 || nbt / 2 >= need)) nbt /= 2;
   Tile t{4, 1, 1, 0};
-  if (!p->vec16) {
+  if (lds_bytes(p->prec, p->Kpad, 1) > kLdsMax) {
+    t = Tile{4, 2, 2, -1};  // one beam tile's weights do not fit LDS
+  } else if (!p->vec16) {
     t = nbt == 8 ? Tile{4, 8, 2, 0} : Tile{4, 1, 1, 0};
   } else if (nch == 1 && nbt >= 4) {
     t = (p->prec == BF_FP32 || p->in4 || p->cx) ? Tile{4, nbt, 1, 1} : Tile{8, nbt, 1, 1};
@@ -199,6 +205,7 @@ void choose_tile(bf_plan_s* p) {
   if (!tile_ok(p, t) && nbt >= 2) t = Tile{4, nbt, 2, 0};
   if (!tile_ok(p, t) && nbt >= 2) t = Tile{4, 2, 2, 0};
   if (!tile_ok(p, t)) t = Tile{4, 1, 1, 0};
+  if (!tile_ok(p, t)) t = Tile{4, 2, 2, -1};
   int32_t G, QI, SG;
   schedule(p->I, p->T, &G, &QI, &SG);
   const int32_t base = t.mt / gcd(t.mt, G);  // sgw * G must be a multiple of MT
@@ -271,6 +278,8 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
     const bf_plan_s* p = plans[i];
     if (!x[i] || !out[i] || !aligned16(x[i]) || !aligned16(out[i])) return BF_ERR_INVALID_ARG;
     if (!p->weights_set) return BF_ERR_STATE;
+    // the batching kernels stage weights in LDS
+    if (lds_bytes(p->prec, p->Kpad, 1) > lds_cap) return BF_ERR_UNSUPPORTED;
   }
   int64_t begin = 0;
   size_t lds = 0;
@@ -452,10 +461,6 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
     }
     (void)hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
     if (p->n_cu < 1) p->n_cu = 256;
-    if (lds_bytes(p->prec, p->Kpad, 1) > kLdsMax) {
-      delete p;
-      return BF_ERR_UNSUPPORTED;
-    }
     choose_tile(p);
     p->w_bytes = (size_t)C * p->Bpad * 2 * p->Kpad * es_of(p->prec);
     hipError_t e = hipMalloc(&p->w_dev, p->w_bytes);
@@ -691,7 +696,7 @@ int bf_run(bf_plan_t p, const int8_t* x, float* out, void* stream) {
     const int64_t grid = (L.total_units + 7) / 8 * 8;
     if (grid > 0x7FFFFFFF) return BF_ERR_UNSUPPORTED;
     e = bf::launch_beamform(p->prec, p->mode, p->vec16, p->in4, p->tile, L, (int)grid,
-                            lds_bytes(p->prec, p->Kpad, p->tile.nbt), s);
+                            tile_lds(p->prec, p->Kpad, p->tile), s);
     if (e == hipSuccess) e = mark_used(p, s);
     return from_hip(e);
   } catch (...) {
@@ -717,7 +722,7 @@ int bf_plan_info(bf_plan_t p, bf_plan_info_t* info) {
   info->sg_per_wave = p->sgw;
   info->work_units = units_for(p, p->tile, p->sgw);
   info->weight_bytes = (int64_t)p->w_bytes;
-  info->lds_bytes = (int64_t)lds_bytes(p->prec, p->Kpad, p->tile.nbt);
+  info->lds_bytes = (int64_t)tile_lds(p->prec, p->Kpad, p->tile);
   info->flops = 8.0 * p->C * (double)p->B * (double)p->T * p->N;
   return BF_OK;
 }

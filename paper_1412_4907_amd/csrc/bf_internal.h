@@ -61,25 +61,29 @@ struct Tile {
 };
 
 // Compiled tile variants: (MT, NBT, NBP, KRES).  KRES > 0 variants serve
-// plans with Kpad / 64 <= KRES.  The generic (byte-load) list serves
-// plans whose 2N is not a multiple of 16.
+// plans with Kpad / 64 <= KRES; KRES == 0 streams K with the unit's weights
+// in LDS; KRES < 0 streams K with the weights read from device memory (any
+// K: arrays whose weight rows do not fit LDS).  The generic (byte-load)
+// list serves plans whose 2N is not a multiple of 16.
 #define BF_TILE_LIST_VEC16                                                        \
   BF_TILE(8, 8, 1, 1) BF_TILE(4, 8, 2, 1) BF_TILE(4, 8, 1, 1) BF_TILE(8, 4, 1, 1)  \
   BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 1, 2) BF_TILE(4, 8, 2, 0)  \
-  BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 2, 1, 0) BF_TILE(4, 1, 1, 0)
-#define BF_TILE_LIST_GENERIC BF_TILE(4, 8, 2, 0) BF_TILE(4, 1, 1, 0)
+  BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 2, 1, 0) BF_TILE(4, 1, 1, 0)  \
+  BF_TILE(4, 2, 2, -1)
+#define BF_TILE_LIST_GENERIC BF_TILE(4, 8, 2, 0) BF_TILE(4, 1, 1, 0) BF_TILE(4, 2, 2, -1)
 // Variants compiled for 4-bit input.
 #define BF_TILE_LIST_IN4                                                          \
   BF_TILE(4, 8, 1, 1) BF_TILE(4, 8, 2, 1) BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2)  \
-  BF_TILE(4, 8, 2, 0) BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 1, 1, 0)
-// Variants compiled into the persistent batching kernel (16-byte loads).
-// (MT = 8 variants are left out: their register use would halve the
-// kernel's occupancy for every set.)
+  BF_TILE(4, 8, 2, 0) BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 1, 1, 0)  \
+  BF_TILE(4, 2, 2, -1)
 // Variants compiled for complex beam output (16-byte rows; byte-load plans
 // use the generic list).
 #define BF_TILE_LIST_CX                                                           \
   BF_TILE(4, 8, 1, 1) BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 8, 2, 0)  \
-  BF_TILE(4, 2, 2, 0) BF_TILE(4, 1, 1, 0)
+  BF_TILE(4, 2, 2, 0) BF_TILE(4, 1, 1, 0) BF_TILE(4, 2, 2, -1)
+// Variants compiled into the persistent batching kernel (16-byte loads).
+// (MT = 8 variants are left out: their register use would halve the
+// kernel's occupancy for every set.)
 #define BF_TILE_LIST_MULTI                                                        \
   BF_TILE(4, 8, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0)  \
   BF_TILE(4, 1, 1, 0)

@@ -264,24 +264,75 @@ def test_error_paths(gpu):
         assert float(p.abs().sum()) == 0.0
 
 
-# --- the largest arrays this build supports -----------------------------------
-# Each work unit keeps its beams' weights for all K = 2N in LDS: N <= 1248 in
-# FP16/BF16 and N <= 608 in FP32; one antenna group (8) more is rejected.
+# --- large arrays -----------------------------------------------------------
+# Up to N = 1248 (FP16/BF16) or 608 (FP32) a work unit keeps its beams'
+# weights for all K = 2N in LDS; beyond, the plan reads weight fragments
+# from device memory (tile kres = -1), up to the API's N = 4096.  Checked
+# against the oracle on both sides of the switch and at N = 4096, and the
+# device-memory tile bit for bit against the LDS tiles where both run.
 
-@pytest.mark.parametrize("prec,n_max", [("fp32", 608), ("fp16", 1248), ("bf16", 1248)])
-def test_largest_supported_array(gpu, prec, n_max):
-    print(f"largest array {prec} N={n_max}", flush=True)
-    g = np.random.default_rng(n_max)
+LARGE = [("fp32", 608, 0), ("fp32", 616, -1), ("fp16", 1248, 0), ("fp16", 1256, -1),
+         ("bf16", 1256, -1), ("fp32", 4096, -1), ("fp16", 4096, -1), ("bf16", 4096, -1)]
+
+
+@pytest.mark.parametrize("prec,n_ant,kres", LARGE, ids=[f"{p}-N{n}" for p, n, _ in LARGE])
+def test_large_arrays(gpu, prec, n_ant, kres):
+    print(f"large array {prec} N={n_ant}", flush=True)
+    g = np.random.default_rng(n_ant + len(prec))
     C, B, T, I = 2, 20, 96, 4
-    pos = synth.disc_positions(n_max, 400.0, g)
+    pos = synth.disc_positions(n_ant, 400.0, g)
     dirs = synth.random_dirs(B, g)
     freqs = np.array([401e6, 414e6])
-    x = g.integers(-128, 128, (C, T, n_max, 2)).astype(np.int8)
-    with bf.Plan(n_max, C, B, T, I, precision=prec) as plan:
+    x = g.integers(-128, 128, (C, T, n_ant, 2)).astype(np.int8)
+    with bf.Plan(n_ant, C, B, T, I, precision=prec) as plan:
         plan.set_weights(pos, dirs, freqs)
+        assert plan.tile()[3] == kres
         got = run_plan(plan, x, gpu)
     ref = oracle.beamform(oracle.weights(pos, dirs, freqs), x, I)
-    assert_parity(got, ref, TOL[prec], f"N={n_max} {prec}")
-    with pytest.raises(bf.BfError) as e:
-        bf.Plan(n_max + 8, C, B, T, I, precision=prec)
-    assert e.value.status == bf.ERR_UNSUPPORTED
+    assert_parity(got, ref, TOL[prec], f"N={n_ant} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_device_memory_weights_tile_bitwise(gpu, prec):
+    """At N = 256 both the LDS tiles and the device-memory tile run: same bits."""
+    g = np.random.default_rng(77)
+    N, C, B, T, I = 256, 2, 40, 512, 16
+    pos = synth.disc_positions(N, 200.0, g)
+    x = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+    with bf.Plan(N, C, B, T, I, precision=prec) as plan:
+        plan.set_weights(pos, synth.random_dirs(B, g), np.array([402e6, 409e6]))
+        base = run_plan(plan, x, gpu)
+        plan.set_tile(4, 2, 2, -1, 4)
+        assert np.array_equal(run_plan(plan, x, gpu), base)
+
+
+def test_large_array_4bit_complex_and_batch(gpu):
+    g = np.random.default_rng(4096)
+    N, C, B, T = 4096, 1, 17, 64
+    pos = synth.disc_positions(N, 400.0, g)
+    dirs = synth.random_dirs(B, g)
+    freqs = np.array([405e6])
+    x4 = g.integers(0, 256, (C, T, N)).astype(np.uint8)
+    W = oracle.weights(pos, dirs, freqs)
+    import torch
+    with bf.Plan(N, C, B, T, 8, precision="fp16", input_bits=4) as plan:
+        plan.set_weights(pos, dirs, freqs)
+        got = run_plan(plan, x4, gpu)
+        batch = bf.Batch([plan])
+        with pytest.raises(bf.BfError) as e:  # the batching kernels stage weights in LDS
+            batch.run([torch.from_numpy(x4).to(gpu)],
+                      [torch.empty((C, B, T // 8), device=gpu)])
+        assert e.value.status == bf.ERR_UNSUPPORTED
+        batch.destroy()
+    assert_parity(got, oracle.beamform(W, oracle.unpack4(x4), 8), TOL["fp16"], "N=4096 4-bit")
+    with bf.Plan(N, C, B, T, 1, precision="fp16", output="complex") as plan:
+        plan.set_weights(pos, dirs, freqs)
+        plan.set_output_scale(1.0 / 64)
+        p = torch.empty(plan.p_shape, dtype=torch.float16, device=gpu)
+        plan.run(torch.from_numpy(oracle.unpack4(x4)).to(gpu), p)
+        torch.cuda.synchronize()
+        o = p.cpu().numpy().astype(np.float64)
+    got_c = o[..., 0] + 1j * o[..., 1]
+    ref_c = oracle.beams(W, oracle.unpack4(x4)) / 64
+    rms = np.sqrt(np.mean(np.abs(ref_c) ** 2, axis=-1, keepdims=True))
+    assert np.max(np.abs(got_c - ref_c) / (np.abs(ref_c) + rms)) <= 2e-3
