@@ -113,7 +113,7 @@ const char* bf_last_hip_error(void);
  * Work units stage their beams' weights for all K = 2N in LDS up to
  * N = 1248 (FP16/BF16) or N = 608 (FP32); larger arrays read the weight
  * fragments from device memory instead (tile kres = -1, chosen
- * automatically; slower, and not accepted by the batching and table forms).
+ * automatically; not accepted by the batching and table forms).
  * Errors: BF_ERR_INVALID_ARG (sizes, null out, unknown precision or flags),
  * BF_ERR_UNSUPPORTED (an unsupported flag combination such as 4-bit input
  * with N % 8 != 0), BF_ERR_OOM, BF_ERR_HIP.
