@@ -469,7 +469,7 @@ def main():
         library_gemm()
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                           "(channel-sharded multi-GPU operation is a design note only)"}))
         sys.exit(2)
     import torch

@@ -66,7 +66,7 @@ enum {
   BF_ERR_OOM = -2,         /* device or pinned-host allocation failed             */
   BF_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed          */
   BF_ERR_STATE = -4,       /* e.g. bf_run before any weights were set             */
-  BF_ERR_UNSUPPORTED = -5  /* valid request outside what this build implements    */
+  BF_ERR_UNSUPPORTED = -5  /* valid request outside what the library implements   */
 };
 
 /* Plan flags. */
@@ -247,7 +247,7 @@ int bf_plan_info(bf_plan_t plan, bf_plan_info_t* info);
  * K with the unit's weights in LDS, -1 = streamed K with the weights read
  * from device memory), sg_per_wave 16-window store groups per wave per work
  * unit.  A
- * combination this build does not compile, or that the plan's K or LDS
+ * combination the library does not compile, or that the plan's K or LDS
  * budget excludes, returns BF_ERR_UNSUPPORTED and leaves the plan unchanged;
  * sg_per_wave * (row tiles per store group) must be a multiple of mt
  * (else BF_ERR_INVALID_ARG).  The choice never changes the results.
