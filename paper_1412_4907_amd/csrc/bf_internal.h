@@ -69,7 +69,7 @@ struct Tile {
   BF_TILE(8, 8, 1, 1) BF_TILE(4, 8, 2, 1) BF_TILE(4, 8, 1, 1) BF_TILE(8, 4, 1, 1)  \
   BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 1, 2) BF_TILE(4, 8, 2, 0)  \
   BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 2, 1, 0) BF_TILE(4, 1, 1, 0)  \
-  BF_TILE(4, 2, 2, -1)
+  BF_TILE(4, 2, 2, -1) BF_TILE(8, 1, 1, -1)
 #define BF_TILE_LIST_GENERIC BF_TILE(4, 8, 2, 0) BF_TILE(4, 1, 1, 0) BF_TILE(4, 2, 2, -1)
 // Variants compiled for 4-bit input.
 #define BF_TILE_LIST_IN4                                                          \
