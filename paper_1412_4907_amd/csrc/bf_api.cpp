@@ -534,11 +534,21 @@ int bf_set_weights_async(bf_plan_t p, const double* pos, const double* dir, cons
     if (!p) return BF_ERR_INVALID_ARG;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (!p->w_alt) {
-      hipError_t e = hipMalloc(&p->w_alt, p->w_bytes);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->w_ready, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->used_cur, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->used_alt, hipEventDisableTiming);
-      if (e != hipSuccess) return from_hip(e);
+      void* alt = nullptr;
+      hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+      hipError_t e = hipMalloc(&alt, p->w_bytes);
+      for (int i = 0; i < 3 && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+      if (e != hipSuccess) {  // leave the plan as it was
+        for (hipEvent_t x : ev)
+          if (x) (void)hipEventDestroy(x);
+        if (alt) (void)hipFree(alt);
+        return from_hip(e);
+      }
+      p->w_alt = alt;
+      p->w_ready = ev[0];
+      p->used_cur = ev[1];
+      p->used_alt = ev[2];
     }
     // the runs that read the spare buffer must have finished (an event never
     // recorded is complete), and a refresh not yet taken is overwritten in
