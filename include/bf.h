@@ -104,6 +104,44 @@ const char* bf_version(void);
 const char* bf_last_hip_error(void);
 
 /*
+ * Tile cache (Sec. 2.2 tunes the K20 kernel's thread and accumulator counts
+ * by sweeping them on the device; the autotuner here times the compiled tile
+ * variants and writes the fastest per problem shape to a JSON file).
+ *
+ * bf_tune_load reads such a file (path: host NUL-terminated string) into a
+ * process-wide table that replaces any table loaded before; it returns the
+ * number of entries read (>= 0), or BF_ERR_INVALID_ARG if the file cannot be
+ * read or is not a JSON object.  Entries are {"<key>": {"tile": [mt, nbt,
+ * nbp, kres, sg_per_wave], ...}, ...}; entries without such a tile are
+ * skipped.  If nothing was loaded explicitly, the first plan creation reads
+ * the file named by the environment variable BF_TUNE_CACHE, if set.
+ * From then on bf_plan_create[_ex] gives a plan the cached tile for its
+ * shape when the table has one that can run it (else the built-in choice).
+ * Thread-safe.
+ */
+int bf_tune_load(const char* path);
+
+/*
+ * The cache key of a plan's shape (for the autotuner that writes the file):
+ * "gfx950/p<precision>/N<N>/B~<b>/I<I>/C~<c>/T~<t>" followed by "/in4" for
+ * 4-bit input, "/cx" for complex output and "/batch" if batch != 0 (the
+ * entry for the batching and table kernels), where b, c, t are the largest
+ * powers of two not above B, C and T.  Writes the NUL-terminated key into
+ * buf (len bytes) and returns its length, or BF_ERR_INVALID_ARG (null plan
+ * or buffer, buffer too small).
+ */
+int bf_tune_key(bf_plan_t plan, int32_t batch, char* buf, int32_t len);
+
+/*
+ * Gives the plan the loaded cache's tile for its shape: the single-run entry
+ * (batch == 0, as at creation) or the batching kernels' entry (batch != 0,
+ * for a plan about to join a bf_batch or bf_table).  Returns 1 if a tile was
+ * applied, 0 if the cache has no usable entry (the plan is unchanged), or
+ * BF_ERR_INVALID_ARG (null plan).
+ */
+int bf_plan_apply_tuned(bf_plan_t plan, int32_t batch);
+
+/*
  * Create a plan for N antennas, C channels, B beams, T samples per block and
  * integration I (all >= 1, T % I == 0, N <= 4096, B <= 65536, C <= 2^24).
  * bf_plan_create makes an FP32 plan with no flags.  The plan allocates its
@@ -150,8 +188,8 @@ int bf_set_weights(bf_plan_t plan, const double* ant_xyz_m, const double* beam_d
  * generation to finish and then reads the new weights; runs enqueued before
  * that keep the previous ones.  The generation itself waits on the device
  * for the runs that last read the spare buffer.  The first call allocates
- * the spare buffer (the size of the weight buffer) and three events, kept
- * until bf_plan_destroy.  A later bf_set_weights or bf_set_weights_raw
+ * the spare buffer (the size of the weight buffer), kept until
+ * bf_plan_destroy.  A later bf_set_weights or bf_set_weights_raw
  * supersedes a refresh not yet taken by a run.  The host arrays are copied
  * before return (the call may wait for the previous weight generation of
  * the plan to finish reading its staging area).  Plans refreshed this way
@@ -215,8 +253,9 @@ int bf_get_weights(bf_plan_t plan, double* weights_out, void* stream);
  * [C][B][T][2] for a BF_OUTPUT_COMPLEX plan); both 16-byte aligned and not
  * overlapping.  Enqueues
  * one kernel on `stream`; no host synchronisation, no allocation.
- * Errors: BF_ERR_INVALID_ARG (null or misaligned pointer), BF_ERR_STATE
- * (weights never set), BF_ERR_HIP (launch failure).
+ * Errors: BF_ERR_INVALID_ARG (null or misaligned pointer, the two byte
+ * ranges overlap), BF_ERR_STATE (weights never set), BF_ERR_HIP (launch
+ * failure).
  */
 int bf_run(bf_plan_t plan, const int8_t* x_dev, float* p_dev, void* stream);
 
@@ -237,6 +276,7 @@ typedef struct {
   int64_t weight_bytes;   /* device bytes of the weight buffer                  */
   int64_t lds_bytes;      /* LDS per workgroup                                  */
   double flops;           /* 8 * C * B * T * N                                  */
+  int32_t tile_tuned;     /* 1 if the tile came from the tile cache             */
 } bf_plan_info_t;
 int bf_plan_info(bf_plan_t plan, bf_plan_info_t* info);
 
@@ -272,7 +312,12 @@ int bf_plan_set_output_scale(bf_plan_t plan, float scale);
  */
 int bf_plan_tile_candidates(bf_plan_t plan, int32_t* tiles, int32_t max_tiles);
 
-/* Free the plan.  Waits for the plan's outstanding device work first.
+/* Free the plan.  Waits first for the plan's own outstanding device work --
+ * weight generation, refreshes, and the bf_run / bf_batch_run /
+ * bf_beam_pattern launches that read its weights -- through events the plan
+ * records, never for other work on the device.  Launches of a bf_table that
+ * read the plan are not tracked by the plan: they must have completed (or
+ * the table must hold another set) before the plan is destroyed.
  * NULL is accepted (no-op). */
 int bf_plan_destroy(bf_plan_t plan);
 
@@ -296,11 +341,15 @@ int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n_plans);
 int bf_batch_tile_candidates(bf_plan_t plan, int32_t* tiles, int32_t max_tiles);
 
 /* x_dev[i], p_dev[i]: host arrays of device pointers, one per plan, same
- * layout and alignment rules as bf_run.  One launch on `stream` (after a
- * one-thread queue reset kernel).  Each set's output is bitwise identical to
- * bf_run of that plan alone. */
+ * layout and alignment rules as bf_run; no output may overlap any set's
+ * voltages or another set's output (else BF_ERR_INVALID_ARG).  One launch on
+ * `stream` (after a one-thread queue reset kernel).  Each set's output is
+ * bitwise identical to bf_run of that plan alone. */
 int bf_batch_run(bf_batch_t batch, const int8_t* const* x_dev, float* const* p_dev, void* stream);
 
+/* Free the batch (not its plans) after its own last bf_batch_run has
+ * completed (an event recorded by that run; other device work is not waited
+ * for).  NULL is accepted. */
 int bf_batch_destroy(bf_batch_t batch);
 
 /*
@@ -343,6 +392,10 @@ int bf_table_set(bf_table_t table, const bf_plan_t* plans, const int8_t* const* 
  * share the table and the queue counter. */
 int bf_table_run(bf_table_t table, void* stream);
 
+/* Free the table after its own last bf_table_set and bf_table_run have
+ * completed (an event recorded by each call that was not made during a
+ * graph capture; launches replayed from a captured graph are the caller's to
+ * wait for).  NULL is accepted. */
 int bf_table_destroy(bf_table_t table);
 
 #ifdef __cplusplus

@@ -25,7 +25,8 @@ OUTPUT_COMPLEX = 4
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_STATE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 
 # every entry point declared in include/bf.h
-EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_plan_create",
+EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_tune_load", "bf_tune_key",
+           "bf_plan_apply_tuned", "bf_plan_create",
            "bf_plan_create_ex", "bf_set_weights", "bf_set_weights_async",
            "bf_plan_set_antenna_mask", "bf_beam_pattern", "bf_set_weights_raw", "bf_get_weights",
            "bf_run", "bf_plan_info", "bf_plan_set_tile", "bf_plan_set_output_scale",
@@ -53,7 +54,8 @@ class PlanInfo(ctypes.Structure):
                 ("tile_nbp", ctypes.c_int32), ("tile_kres", ctypes.c_int32),
                 ("sg_per_wave", ctypes.c_int32),
                 ("work_units", ctypes.c_int64), ("weight_bytes", ctypes.c_int64),
-                ("lds_bytes", ctypes.c_int64), ("flops", ctypes.c_double)]
+                ("lds_bytes", ctypes.c_int64), ("flops", ctypes.c_double),
+                ("tile_tuned", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +77,9 @@ def lib() -> ctypes.CDLL:
         L.bf_strerror.argtypes = [ctypes.c_int]
         L.bf_version.restype = ctypes.c_char_p
         L.bf_last_hip_error.restype = ctypes.c_char_p
+        L.bf_tune_load.argtypes = [ctypes.c_char_p]
+        L.bf_tune_key.argtypes = [P, i32, ctypes.c_char_p, i32]
+        L.bf_plan_apply_tuned.argtypes = [P, i32]
         L.bf_plan_create.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32]
         L.bf_plan_create_ex.argtypes = [ctypes.POINTER(P), i32, i32, i32, i64, i32, ctypes.c_int, u32]
         L.bf_set_weights.argtypes = [P, P, P, P, P]
@@ -100,7 +105,21 @@ def lib() -> ctypes.CDLL:
         for name in EXPORTS[3:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
+        # the autotuner's tile cache, applied by the library at plan creation
+        from . import tune
+        path = tune.cache_path()
+        if os.path.exists(path):
+            tune_load(path)
     return _lib
+
+
+def tune_load(path: str) -> int:
+    """Load a tile cache written by the autotuner (``bf_tune_load``); returns
+    the number of entries."""
+    n = lib().bf_tune_load(os.fsencode(path))
+    if n < 0:
+        raise BfError(n, f"bf_tune_load({path})")
+    return n
 
 
 def strerror(status: int) -> str:
@@ -299,6 +318,22 @@ class Plan:
         arr = (ctypes.c_int32 * (4 * max(n, 1)))()
         fn(self.handle, ctypes.addressof(arr), n)
         return [tuple(arr[4 * i:4 * i + 4]) for i in range(n)]
+
+    def tune_key(self, batch: bool = False) -> str:
+        """The tile-cache key of this plan's shape (``bf_tune_key``)."""
+        buf = ctypes.create_string_buffer(256)
+        n = lib().bf_tune_key(self.handle, 1 if batch else 0, buf, 256)
+        if n < 0:
+            raise BfError(n, "bf_tune_key")
+        return buf.value.decode()
+
+    def apply_tuned(self, batch: bool = False) -> bool:
+        """Apply the loaded tile cache's entry for this shape (``batch``: the
+        batching kernel's entry); False if there is none."""
+        r = lib().bf_plan_apply_tuned(self.handle, 1 if batch else 0)
+        if r < 0:
+            raise BfError(r, "bf_plan_apply_tuned")
+        return r == 1
 
     def tile(self) -> tuple:
         i = self.info()

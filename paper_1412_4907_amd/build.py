@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libbf.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["bf_api.cpp", "bf_weights.hip", "bf_pattern.hip", "bf_beamform_f32.hip", "bf_beamform_f16.hip",
+SOURCES = ["bf_api.cpp", "bf_host.cpp", "bf_weights.hip", "bf_pattern.hip", "bf_beamform_f32.hip", "bf_beamform_f16.hip",
            "bf_beamform_bf16.hip", "bf_beamform_f32_in4.hip", "bf_beamform_f16_in4.hip",
            "bf_beamform_bf16_in4.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -26,8 +26,32 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I", os.path.join(ROOT, "include")]
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _includes(path: str, seen=None) -> set:
+    """Files a source includes with #include "...", recursively."""
+    import re
+    seen = set() if seen is None else seen
+    with open(path) as f:
+        text = f.read()
+    for name in re.findall(r'#include\s+"([^"]+)"', text):
+        dep = os.path.normpath(os.path.join(os.path.dirname(path), name))
+        if os.path.exists(dep) and dep not in seen:
+            seen.add(dep)
+            _includes(dep, seen)
+    return seen
+
+
+def _stale(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    path = os.path.join(CSRC, src)
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(f) > t for f in {path} | _includes(path) | {__file__})
+
+
+def _compile(src: str, verbose: bool, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not force and not _stale(src, obj):
+        return obj
     cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, "-x", "hip"] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -40,10 +64,12 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force=False: only those whose object is older
+    than the source, a header it includes or this script) and link."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, force), SOURCES))
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -64,4 +90,4 @@ def source_hash() -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, force="--incremental" not in sys.argv))

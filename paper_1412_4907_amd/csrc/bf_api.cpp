@@ -7,32 +7,27 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/bf.h"
+#include "bf_host.h"
 #include "bf_internal.h"
 
 using bf::Launch;
 using bf::Prob;
 using bf::Tile;
 
-struct bf_plan_s {
-  int32_t N = 0, C = 0, B = 0, I = 0;
-  int64_t T = 0;
-  int prec = 0;
-  uint32_t flags = 0;
-  int32_t Bpad = 0, Kpad = 0;
-  int mode = 0;
-  bool vec16 = true;
-  bool in4 = false;  // 4-bit complex input (one byte per antenna sample)
-  bool cx = false;   // complex beam output (FP16 pairs) instead of power
+struct bf_plan_s : bf::Shape {
   float out_scale = 1.0f;
-  Tile tile{4, 1, 1};
+  Tile tile{4, 1, 1, 0};
   int32_t sgw = 1;
+  bool tuned = false;  // tile taken from the tile cache
   int device = 0;
-  int n_cu = 256;
   size_t w_bytes = 0;
   void* w_dev = nullptr;  // the weights runs read
   bool weights_set = false;
@@ -46,7 +41,10 @@ struct bf_plan_s {
   std::vector<double> mask;  // [N], 1 = antenna used
   // asynchronous refresh (bf_set_weights_async): a second buffer, filled on
   // the caller's stream while runs read w_dev; the next run waits for it and
-  // swaps.  used_cur / used_alt mark the last run that read each buffer.
+  // swaps.  used_cur / used_alt mark the last run that read each buffer;
+  // w_ready the last generation into the spare.  Together with geo_done they
+  // cover every piece of device work the plan enqueues, so destroying a plan
+  // waits for exactly its own work.
   void* w_alt = nullptr;
   hipEvent_t w_ready = nullptr;
   hipEvent_t used_cur = nullptr, used_alt = nullptr;
@@ -57,6 +55,7 @@ struct bf_batch_s {
   std::vector<bf_plan_t> plans;
   int32_t* queue = nullptr;
   int device = 0;
+  hipEvent_t last_use = nullptr;  // recorded after each bf_batch_run
 };
 
 struct bf_table_s {
@@ -70,156 +69,22 @@ struct bf_table_s {
   int n_cu = 256;
   int32_t* queue = nullptr;
   Launch* table = nullptr;  // device copy of the set table
+  hipEvent_t last_use = nullptr;  // recorded after each set and (uncaptured) run
 };
 
 namespace {
 
-constexpr int kMaxN = 4096;
-constexpr int kMaxB = 65536;
-constexpr int kMaxC = 1 << 24;
-constexpr size_t kLdsMax = 160 * 1024 - 256;  // dynamic LDS; the rest is static
-
-int es_of(int prec) { return prec == BF_FP32 ? 4 : 2; }
-
-size_t lds_bytes(int prec, int Kpad, int nbt) {
-  return (size_t)2 * 16 * nbt * ((size_t)Kpad * es_of(prec) + bf::kLdsPad);
-}
-
-// Dynamic LDS of a tile: the unit's weight rows, none when they are read
-// from device memory.
-size_t tile_lds(int prec, int Kpad, Tile t) { return t.kres < 0 ? 0 : lds_bytes(prec, Kpad, t.nbt); }
-
-int mode_of(int32_t I) {
-  return I == 1 ? bf::kModeI1 : I == 2 ? bf::kModeI2 : (I % 4 == 0 ? bf::kModeGen4 : bf::kModeGen);
-}
-
-// Geometry of the row-tile schedule for integration I (see bf_beamform.inc).
-void schedule(int32_t I, int64_t T, int32_t* G, int32_t* QI, int32_t* SG) {
-  int64_t W = T / I;
-  if (I == 1) {
-    *G = 1;
-    *QI = 1;
-  } else if (I == 2) {
-    *G = 2;
-    *QI = 1;
-  } else {
-    *QI = (I + 3) / 4;
-    *G = 4 * *QI;
-  }
-  *SG = (int32_t)((W + 15) / 16);
-}
+using bf::choose_tile;
+using bf::es_of;
+using bf::kLdsMax;
+using bf::lds_bytes;
+using bf::same_tile;
+using bf::schedule;
+using bf::tile_lds;
+using bf::tile_ok;
+using bf::units_for;
 
 int gcd(int a, int b) { return b ? gcd(b, a % b) : a; }
-
-const Tile kVecTiles[] = {
-#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
-    BF_TILE_LIST_VEC16
-#undef BF_TILE
-};
-const Tile kMultiTiles[] = {
-#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
-    BF_TILE_LIST_MULTI
-#undef BF_TILE
-};
-const Tile kGenTiles[] = {
-#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
-    BF_TILE_LIST_GENERIC
-#undef BF_TILE
-};
-const Tile kIn4Tiles[] = {
-#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
-    BF_TILE_LIST_IN4
-#undef BF_TILE
-};
-const Tile kCxTiles[] = {
-#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
-    BF_TILE_LIST_CX
-#undef BF_TILE
-};
-
-bool same_tile(const Tile& a, const Tile& b) {
-  return a.mt == b.mt && a.nbt == b.nbt && a.nbp == b.nbp && a.kres == b.kres;
-}
-
-// The single-set variants compiled for a plan's output, input format and
-// row width.
-template <class F>
-void for_each_tile(const bf_plan_s* p, F f) {
-  if (p->cx && p->vec16)
-    for (const Tile& x : kCxTiles) f(x);
-  else if (p->in4)
-    for (const Tile& x : kIn4Tiles) f(x);
-  else if (p->vec16)
-    for (const Tile& x : kVecTiles) f(x);
-  else
-    for (const Tile& x : kGenTiles) f(x);
-}
-
-bool tile_exists(const bf_plan_s* p, Tile t) {
-  bool found = false;
-  for_each_tile(p, [&](const Tile& x) { found = found || same_tile(x, t); });
-  return found;
-}
-
-// Work units per bf_run for a tile/sgw choice.
-int64_t units_for(const bf_plan_s* p, Tile t, int32_t sgw) {
-  int32_t G, QI, SG;
-  schedule(p->I, p->T, &G, &QI, &SG);
-  int64_t nbr = (p->Bpad / 16 + t.nbt - 1) / t.nbt;
-  int64_t ntr = (SG + (int64_t)bf::kWaves * sgw - 1) / ((int64_t)bf::kWaves * sgw);
-  return (int64_t)p->C * nbr * ntr;
-}
-
-// Whether a compiled tile can run plan p.
-bool tile_ok(const bf_plan_s* p, Tile t) {
-  if (!tile_exists(p, t)) return false;
-  if (t.kres > 0 && p->Kpad / bf::kChunk > t.kres) return false;
-  return tile_lds(p->prec, p->Kpad, t) <= kLdsMax;
-}
-
-// Default tile: the largest beam range whose weight slice fits 80 KB of LDS
-// (two workgroups per CU) without exceeding the plan's beams; voltages held
-// in registers when K <= 128 (MT = 8 for FP16/BF16 at K <= 64, where the
-// per-pass fragment reuse matters most); streamed K otherwise.  Then
-// enough store groups per wave that a launch has >= 8 workgroups per CU,
-// capped at 256 row tiles per wave per unit.
-void choose_tile(bf_plan_s* p) {
-  const int need = p->Bpad / 16;
-  const int nch = p->Kpad / bf::kChunk;
-  int nbt = 8;
-  while (nbt > 1 && (lds_bytes(p->prec, p->Kpad, nbt) > 80 * 1024 || nbt / 2 >= need)) nbt /= 2;
-  Tile t{4, 1, 1, 0};
-  if (lds_bytes(p->prec, p->Kpad, 1) > kLdsMax) {
-    t = Tile{4, 2, 2, -1};  // one beam tile's weights do not fit LDS
-  } else if (!p->vec16) {
-    t = nbt == 8 ? Tile{4, 8, 2, 0} : Tile{4, 1, 1, 0};
-  } else if (nch == 1 && nbt >= 4) {
-    t = (p->prec == BF_FP32 || p->in4 || p->cx) ? Tile{4, nbt, 1, 1} : Tile{8, nbt, 1, 1};
-  } else if (nch == 2 && nbt >= 4) {
-    t = Tile{4, nbt, 1, 2};
-  } else {
-    t = nbt >= 4 ? Tile{4, nbt, 2, 0} : nbt == 2 ? Tile{4, 2, 2, 0} : Tile{4, 1, 1, 0};
-  }
-  // the 4-bit and complex-output variants carry fewer forms: fall back to
-  // the streamed form of the same beam range
-  if (!tile_ok(p, t) && nbt >= 2) t = Tile{4, nbt, 2, 0};
-  if (!tile_ok(p, t) && nbt >= 2) t = Tile{4, 2, 2, 0};
-  if (!tile_ok(p, t)) t = Tile{4, 1, 1, 0};
-  if (!tile_ok(p, t)) t = Tile{4, 2, 2, -1};
-  int32_t G, QI, SG;
-  schedule(p->I, p->T, &G, &QI, &SG);
-  const int32_t base = t.mt / gcd(t.mt, G);  // sgw * G must be a multiple of MT
-  int32_t sgw = base;
-  const int64_t want = (int64_t)p->n_cu * 8;
-  for (int32_t k = 2;; ++k) {
-    int32_t s = base * k;
-    if ((int64_t)s * G > 256 || units_for(p, t, s) < want) break;
-    if ((int64_t)(s - base) * bf::kWaves >= SG) break;
-    sgw = s;
-  }
-  p->tile = t;
-  p->sgw = sgw;
-}
 
 Prob make_prob(const bf_plan_s* p, const int8_t* x, float* out, int64_t unit_begin) {
   Prob q;
@@ -256,6 +121,123 @@ Prob make_prob(const bf_plan_s* p, const int8_t* x, float* out, int64_t unit_beg
 
 thread_local char g_last_error[256] = "no error";
 
+// ---- device memory owned by handles ----
+// hipFree waits for every stream of the device, so handles never use it:
+// their device buffers come from a library-owned stream-ordered pool per
+// device.  An allocation is made on a private stream that carries nothing
+// else (so waiting for it waits for nothing but the allocation), and a
+// handle's buffers are released with hipFreeAsync on a second private
+// stream, after waits on the handle's own events: destroying a handle never
+// waits for, or is ordered behind, other work on the device.  The pool does
+// not let an allocation wait for a pending release (no internal
+// dependencies): memory is reused only once its release has run.
+struct DevMem {
+  hipStream_t alloc = nullptr;
+  hipStream_t release = nullptr;
+  hipMemPool_t pool = nullptr;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_mem_mu;
+DevMem g_mem[kMaxDevices];
+
+hipError_t dev_mem(int dev, DevMem** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_mem_mu);
+  DevMem& d = g_mem[dev];
+  if (!d.pool) {
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    hipStream_t a = nullptr, r = nullptr;
+    hipError_t e = hipMemPoolCreate(&pool, &props);
+    int zero = 0;
+    if (e == hipSuccess)
+      e = hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowInternalDependencies, &zero);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&r, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      if (a) (void)hipStreamDestroy(a);
+      if (r) (void)hipStreamDestroy(r);
+      if (pool) (void)hipMemPoolDestroy(pool);
+      return e;
+    }
+    d.pool = pool;
+    d.alloc = a;
+    d.release = r;
+  }
+  *out = &d;
+  return hipSuccess;
+}
+
+// n bytes of device memory on `dev`, usable from any stream on return.
+hipError_t dev_alloc(int dev, void** ptr, size_t n) {
+  *ptr = nullptr;
+  DevMem* d = nullptr;
+  hipError_t e = dev_mem(dev, &d);
+  if (e != hipSuccess) return e;
+  e = hipMallocFromPoolAsync(ptr, n, d->pool, d->alloc);
+  if (e == hipSuccess) e = hipStreamSynchronize(d->alloc);
+  if (e != hipSuccess && *ptr) {
+    (void)hipFreeAsync(*ptr, d->alloc);
+    *ptr = nullptr;
+  }
+  return e;
+}
+
+// Releases device buffers of `dev` once every event in `after` has
+// completed (events never recorded count as complete); does not wait.
+hipError_t dev_release(int dev, std::initializer_list<hipEvent_t> after,
+                       std::initializer_list<void*> ptrs) {
+  DevMem* d = nullptr;
+  hipError_t e = dev_mem(dev, &d);
+  if (e != hipSuccess) return e;
+  for (hipEvent_t ev : after)
+    if (ev && e == hipSuccess) e = hipStreamWaitEvent(d->release, ev, 0);
+  for (void* ptr : ptrs)
+    if (ptr && e == hipSuccess) e = hipFreeAsync(ptr, d->release);
+  return e;
+}
+
+// Pinned host staging buffers are recycled rather than freed (hipHostFree
+// may wait for the device): a released buffer is kept for a later plan.
+struct Pinned {
+  void* p;
+  size_t n;
+};
+std::mutex g_pin_mu;
+std::vector<Pinned> g_pinned;
+
+hipError_t pinned_acquire(size_t n, void** out) {
+  {
+    std::lock_guard<std::mutex> lock(g_pin_mu);
+    size_t best = g_pinned.size();
+    for (size_t i = 0; i < g_pinned.size(); ++i)
+      if (g_pinned[i].n >= n && (best == g_pinned.size() || g_pinned[i].n < g_pinned[best].n))
+        best = i;
+    if (best < g_pinned.size()) {
+      *out = g_pinned[best].p;
+      g_pinned.erase(g_pinned.begin() + (std::ptrdiff_t)best);
+      return hipSuccess;
+    }
+  }
+  // round up so that buffers are reusable across nearby sizes
+  size_t cap = 4096;
+  while (cap < n) cap *= 2;
+  return hipHostMalloc(out, cap, 0);
+}
+
+void pinned_release(void* p, size_t n) {
+  if (!p) return;
+  size_t cap = 4096;
+  while (cap < n) cap *= 2;
+  std::lock_guard<std::mutex> lock(g_pin_mu);
+  g_pinned.push_back(Pinned{p, cap});
+}
+
 int from_hip(hipError_t e) {
   if (e == hipSuccess) return BF_OK;
   (void)hipGetLastError();  // the status is returned; do not leave it pending for others
@@ -281,6 +263,16 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
     // the batching kernels stage weights in LDS
     if (lds_bytes(p->prec, p->Kpad, 1) > lds_cap) return BF_ERR_UNSUPPORTED;
   }
+  // no set's output may overlap any set's voltages or another set's output
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      if (bf::ranges_overlap(out[i], bf::output_bytes(*plans[i]), x[j],
+                             bf::input_bytes(*plans[j])))
+        return BF_ERR_INVALID_ARG;
+      if (j > i && bf::ranges_overlap(out[i], bf::output_bytes(*plans[i]), out[j],
+                                      bf::output_bytes(*plans[j])))
+        return BF_ERR_INVALID_ARG;
+    }
   int64_t begin = 0;
   size_t lds = 0;
   const bool multi = plans[0]->vec16;
@@ -292,7 +284,7 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
                      [](const Tile& a, const Tile& b) { return a.nbt > b.nbt; });
     for (const Tile& c : cand) {
       bool ok = true;
-      for (int i = 0; i < n && ok; ++i) ok = tile_ok(plans[i], c);
+      for (int i = 0; i < n && ok; ++i) ok = tile_ok(*plans[i], c);
       if (ok) {
         *common = c;
         break;
@@ -304,9 +296,10 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
     Tile t = *common;
     int variant = -1;
     if (multi) {
-      const int nm = (int)(sizeof(kMultiTiles) / sizeof(kMultiTiles[0]));
+      const std::vector<Tile> kMultiTiles = bf::multi_tiles();
+      const int nm = (int)kMultiTiles.size();
       auto fits = [&](const Tile& c) {
-        return tile_ok(&tmp, c) && lds_bytes(tmp.prec, tmp.Kpad, c.nbt) <= lds_cap;
+        return tile_ok(tmp, c) && lds_bytes(tmp.prec, tmp.Kpad, c.nbt) <= lds_cap;
       };
       for (int v = 0; v < nm && variant < 0; ++v) {
         const Tile& c = kMultiTiles[v];
@@ -332,7 +325,7 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
     tmp.sgw = same ? tmp.sgw : std::max(base, tmp.sgw / base * base);
     L->prob[i] = make_prob(&tmp, x[i], out[i], begin);
     L->prob[i].variant = variant;
-    begin += units_for(&tmp, t, tmp.sgw);
+    begin += units_for(tmp, t, tmp.sgw);
     lds = std::max(lds, lds_bytes(tmp.prec, tmp.Kpad, t.nbt));
   }
   if (lds > lds_cap) return BF_ERR_UNSUPPORTED;
@@ -399,8 +392,60 @@ hipError_t take_refresh(bf_plan_s* p, hipStream_t s) {
 }
 
 // After a launch on s that read the plan's current buffer.
-hipError_t mark_used(bf_plan_s* p, hipStream_t s) {
-  return p->used_cur ? hipEventRecord(p->used_cur, s) : hipSuccess;
+hipError_t mark_used(bf_plan_s* p, hipStream_t s) { return hipEventRecord(p->used_cur, s); }
+
+// Records ev on s, except while s is being captured into a graph (a replay
+// of the graph is then tracked by the caller, not by the event).
+hipError_t record_unless_capturing(hipEvent_t ev, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return e;
+  return cs == hipStreamCaptureStatusNone ? hipEventRecord(ev, s) : hipSuccess;
+}
+
+// ---- tile cache (written by the autotuner, read here) ----
+std::mutex g_tune_mu;
+std::vector<bf::TuneEntry> g_tune;
+bool g_tune_env_tried = false;
+
+int load_tune_file(const char* path, std::vector<bf::TuneEntry>* out) {
+  std::FILE* f = std::fopen(path, "rb");
+  if (!f) return BF_ERR_INVALID_ARG;
+  std::string text;
+  char buf[65536];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) {
+    text.append(buf, n);
+    if (text.size() > ((size_t)64 << 20)) {  // not a tile cache
+      std::fclose(f);
+      return BF_ERR_INVALID_ARG;
+    }
+  }
+  std::fclose(f);
+  const int k = bf::parse_tune_cache(text.data(), text.size(), out);
+  return k < 0 ? BF_ERR_INVALID_ARG : k;
+}
+
+// Applies the cache entry for the plan's shape (single-run or batching
+// kernel), if one exists and its tile can run the plan.  Returns whether a
+// tile was applied.
+bool apply_tuned(bf_plan_s* p, bool batch) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  if (!g_tune_env_tried) {
+    g_tune_env_tried = true;
+    const char* env = std::getenv("BF_TUNE_CACHE");
+    if (env && *env && g_tune.empty()) (void)load_tune_file(env, &g_tune);
+  }
+  const std::string key = bf::tune_key(*p, batch);
+  for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it) {
+    if (it->key != key) continue;
+    if (bf::check_tile(*p, it->tile, it->sgw) != BF_OK) return false;
+    p->tile = it->tile;
+    p->sgw = it->sgw;
+    p->tuned = true;
+    return true;
+  }
+  return false;
 }
 
 }  // namespace
@@ -421,6 +466,42 @@ const char* bf_strerror(int status) {
 
 const char* bf_version(void) { return "bf 0.1 gfx950"; }
 
+int bf_tune_load(const char* path) {
+  try {
+    if (!path) return BF_ERR_INVALID_ARG;
+    std::vector<bf::TuneEntry> got;
+    const int k = load_tune_file(path, &got);
+    if (k < 0) return k;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_env_tried = true;  // an explicit load replaces the environment's
+    g_tune.swap(got);
+    return k;
+  } catch (...) {
+    return BF_ERR_OOM;
+  }
+}
+
+int bf_tune_key(bf_plan_t p, int32_t batch, char* buf, int32_t len) {
+  try {
+    if (!p || !buf || len < 1) return BF_ERR_INVALID_ARG;
+    const std::string k = bf::tune_key(*p, batch != 0);
+    if ((size_t)len < k.size() + 1) return BF_ERR_INVALID_ARG;
+    std::memcpy(buf, k.c_str(), k.size() + 1);
+    return (int)k.size();
+  } catch (...) {
+    return BF_ERR_OOM;
+  }
+}
+
+int bf_plan_apply_tuned(bf_plan_t p, int32_t batch) {
+  try {
+    if (!p) return BF_ERR_INVALID_ARG;
+    return apply_tuned(p, batch != 0) ? 1 : 0;
+  } catch (...) {
+    return BF_ERR_OOM;
+  }
+}
+
 const char* bf_last_hip_error(void) { return g_last_error; }
 
 int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T, int32_t I,
@@ -428,42 +509,22 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
   try {
     if (!out) return BF_ERR_INVALID_ARG;
     *out = nullptr;
-    if (N < 1 || N > kMaxN || C < 1 || C > kMaxC || B < 1 || B > kMaxB || T < 1 || I < 1 ||
-        T % I != 0 || T > ((int64_t)1 << 40))
-      return BF_ERR_INVALID_ARG;
-    if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
-      return BF_ERR_INVALID_ARG;
-    if (flags & ~(BF_ACCUMULATE | BF_INPUT_4BIT | BF_OUTPUT_COMPLEX)) return BF_ERR_INVALID_ARG;
-    // complex beams are per sample and overwrite their output
-    if ((flags & BF_OUTPUT_COMPLEX) && (I != 1 || (flags & BF_ACCUMULATE)))
-      return BF_ERR_INVALID_ARG;
-    // 4-bit rows are read 8 bytes (8 antennas) at a time
-    if ((flags & BF_INPUT_4BIT) && N % 8 != 0) return BF_ERR_UNSUPPORTED;
+    bf::Shape sh;
+    const int st = bf::make_shape(N, C, B, T, I, (int)precision, flags, 256, &sh);
+    if (st != BF_OK) return st;
     bf_plan_s* p = new (std::nothrow) bf_plan_s();
     if (!p) return BF_ERR_OOM;
-    p->N = N;
-    p->C = C;
-    p->B = B;
-    p->T = T;
-    p->I = I;
-    p->prec = precision;
-    p->flags = flags;
-    p->Bpad = (B + 15) / 16 * 16;
-    p->Kpad = (2 * N + bf::kChunk - 1) / bf::kChunk * bf::kChunk;
-    p->mode = mode_of(I);
-    p->vec16 = (2 * N) % 16 == 0;
-    p->in4 = (flags & BF_INPUT_4BIT) != 0;
-    p->cx = (flags & BF_OUTPUT_COMPLEX) != 0;
-    if (p->cx) p->mode = bf::kModeCx;
+    static_cast<bf::Shape&>(*p) = sh;
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;
       return BF_ERR_HIP;
     }
     (void)hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
     if (p->n_cu < 1) p->n_cu = 256;
-    choose_tile(p);
+    choose_tile(*p, &p->tile, &p->sgw);
+    apply_tuned(p, false);
     p->w_bytes = (size_t)C * p->Bpad * 2 * p->Kpad * es_of(p->prec);
-    hipError_t e = hipMalloc(&p->w_dev, p->w_bytes);
+    hipError_t e = dev_alloc(p->device, &p->w_dev, p->w_bytes);
     if (e != hipSuccess) {
       delete p;
       return from_hip(e);
@@ -472,9 +533,12 @@ int bf_plan_create_ex(bf_plan_t* out, int32_t N, int32_t C, int32_t B, int64_t T
     // (padding included), and nothing reads it before one of them has run
     p->geo_count = (size_t)3 * N + (size_t)3 * B + (size_t)C + (size_t)N;
     p->mask.assign(N, 1.0);
-    e = hipHostMalloc((void**)&p->geo_host, p->geo_count * sizeof(double), 0);
-    if (e == hipSuccess) e = hipMalloc(&p->geo_dev, p->geo_count * sizeof(double));
+    e = pinned_acquire(p->geo_count * sizeof(double), (void**)&p->geo_host);
+    if (e == hipSuccess) e = dev_alloc(p->device, (void**)&p->geo_dev, p->geo_count * sizeof(double));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->geo_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->used_cur, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->used_alt, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->w_ready, hipEventDisableTiming);
     if (e != hipSuccess) {
       bf_plan_destroy(p);
       return from_hip(e);
@@ -496,15 +560,18 @@ int bf_plan_destroy(bf_plan_t p) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipSetDevice(p->device);
-    (void)hipDeviceSynchronize();
-    if (p->w_dev) (void)hipFree(p->w_dev);
-    if (p->geo_dev) (void)hipFree(p->geo_dev);
-    if (p->geo_host) (void)hipHostFree(p->geo_host);
-    if (p->geo_done) (void)hipEventDestroy(p->geo_done);
-    if (p->w_alt) (void)hipFree(p->w_alt);
-    if (p->w_ready) (void)hipEventDestroy(p->w_ready);
-    if (p->used_cur) (void)hipEventDestroy(p->used_cur);
-    if (p->used_alt) (void)hipEventDestroy(p->used_alt);
+    // device buffers: released on the device after the plan's own work
+    // (weight generation, refreshes, the runs that read either buffer)
+    (void)dev_release(p->device, {p->geo_done, p->w_ready, p->used_cur, p->used_alt},
+                      {p->w_dev, p->w_alt, p->geo_dev});
+    // the pinned staging area is reused by later plans once the copy that
+    // read it (ordered before geo_done) is done
+    if (p->geo_host) {
+      if (p->geo_done) (void)hipEventSynchronize(p->geo_done);
+      pinned_release(p->geo_host, p->geo_count * sizeof(double));
+    }
+    for (hipEvent_t ev : {p->geo_done, p->w_ready, p->used_cur, p->used_alt})
+      if (ev) (void)hipEventDestroy(ev);
     (void)hipSetDevice(dev);
     delete p;
     return BF_OK;
@@ -535,20 +602,9 @@ int bf_set_weights_async(bf_plan_t p, const double* pos, const double* dir, cons
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (!p->w_alt) {
       void* alt = nullptr;
-      hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-      hipError_t e = hipMalloc(&alt, p->w_bytes);
-      for (int i = 0; i < 3 && e == hipSuccess; ++i)
-        e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
-      if (e != hipSuccess) {  // leave the plan as it was
-        for (hipEvent_t x : ev)
-          if (x) (void)hipEventDestroy(x);
-        if (alt) (void)hipFree(alt);
-        return from_hip(e);
-      }
+      hipError_t e = dev_alloc(p->device, &alt, p->w_bytes);
+      if (e != hipSuccess) return from_hip(e);  // the plan is left as it was
       p->w_alt = alt;
-      p->w_ready = ev[0];
-      p->used_cur = ev[1];
-      p->used_alt = ev[2];
     }
     // the runs that read the spare buffer must have finished (an event never
     // recorded is complete), and a refresh not yet taken is overwritten in
@@ -692,6 +748,8 @@ int bf_get_weights(bf_plan_t p, double* out, void* stream) {
 int bf_run(bf_plan_t p, const int8_t* x, float* out, void* stream) {
   try {
     if (!p || !x || !out || !aligned16(x) || !aligned16(out)) return BF_ERR_INVALID_ARG;
+    if (bf::ranges_overlap(x, bf::input_bytes(*p), out, bf::output_bytes(*p)))
+      return BF_ERR_INVALID_ARG;
     if (!p->weights_set && !p->refresh_pending) return BF_ERR_STATE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = take_refresh(p, s);
@@ -700,7 +758,7 @@ int bf_run(bf_plan_t p, const int8_t* x, float* out, void* stream) {
     std::memset(&L, 0, sizeof(L));
     L.prob[0] = make_prob(p, x, out, 0);
     L.nprob = 1;
-    L.total_units = units_for(p, p->tile, p->sgw);
+    L.total_units = units_for(*p, p->tile, p->sgw);
     L.queue = nullptr;
     L.xcd_remap = 1;
     const int64_t grid = (L.total_units + 7) / 8 * 8;
@@ -730,23 +788,23 @@ int bf_plan_info(bf_plan_t p, bf_plan_info_t* info) {
   info->tile_nbp = p->tile.nbp;
   info->tile_kres = p->tile.kres;
   info->sg_per_wave = p->sgw;
-  info->work_units = units_for(p, p->tile, p->sgw);
+  info->work_units = units_for(*p, p->tile, p->sgw);
   info->weight_bytes = (int64_t)p->w_bytes;
   info->lds_bytes = (int64_t)tile_lds(p->prec, p->Kpad, p->tile);
   info->flops = 8.0 * p->C * (double)p->B * (double)p->T * p->N;
+  info->tile_tuned = p->tuned ? 1 : 0;
   return BF_OK;
 }
 
 int bf_plan_set_tile(bf_plan_t p, int32_t mt, int32_t nbt, int32_t nbp, int32_t kres,
                      int32_t sgw) {
-  if (!p || sgw < 1) return BF_ERR_INVALID_ARG;
-  Tile t{mt, nbt, nbp, kres};
-  if (!tile_ok(p, t)) return BF_ERR_UNSUPPORTED;
-  int32_t G, QI, SG;
-  schedule(p->I, p->T, &G, &QI, &SG);
-  if (((int64_t)sgw * G) % mt != 0) return BF_ERR_INVALID_ARG;
+  if (!p) return BF_ERR_INVALID_ARG;
+  const Tile t{mt, nbt, nbp, kres};
+  const int st = bf::check_tile(*p, t, sgw);
+  if (st != BF_OK) return st;
   p->tile = t;
   p->sgw = sgw;
+  p->tuned = false;
   return BF_OK;
 }
 
@@ -761,7 +819,7 @@ int bf_plan_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
   if (!p || max_tiles < 0 || (max_tiles > 0 && !tiles)) return BF_ERR_INVALID_ARG;
   int32_t n = 0;
   auto add = [&](const Tile& t) {
-    if (!tile_ok(p, t)) return;
+    if (!tile_ok(*p, t)) return;
     if (n < max_tiles) {
       tiles[4 * n + 0] = t.mt;
       tiles[4 * n + 1] = t.nbt;
@@ -770,7 +828,7 @@ int bf_plan_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
     }
     ++n;
   };
-  for_each_tile(p, add);
+  for (const Tile& t : bf::compiled_tiles(*p)) add(t);
   return n;
 }
 
@@ -778,8 +836,8 @@ int bf_batch_tile_candidates(bf_plan_t p, int32_t* tiles, int32_t max_tiles) {
   if (!p || max_tiles < 0 || (max_tiles > 0 && !tiles)) return BF_ERR_INVALID_ARG;
   int32_t n = 0;
   if (!p->vec16 || p->cx) return 0;
-  for (const Tile& t : kMultiTiles) {
-    if (!tile_ok(p, t)) continue;
+  for (const Tile& t : bf::multi_tiles()) {
+    if (!tile_ok(*p, t)) continue;
     if (n < max_tiles) {
       tiles[4 * n + 0] = t.mt;
       tiles[4 * n + 1] = t.nbt;
@@ -809,8 +867,10 @@ int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n) {
     bf_batch_s* bt = new bf_batch_s();
     bt->plans.assign(plans, plans + n);
     bt->device = plans[0]->device;
-    hipError_t e = hipMalloc((void**)&bt->queue, sizeof(int32_t));
+    hipError_t e = dev_alloc(bt->device, (void**)&bt->queue, 256);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->last_use, hipEventDisableTiming);
     if (e != hipSuccess) {
+      (void)dev_release(bt->device, {}, {bt->queue});
       delete bt;
       return from_hip(e);
     }
@@ -856,6 +916,7 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
                                       (int)grid, lds, s);
     }
     for (int i = 0; i < n && e == hipSuccess; ++i) e = mark_used(bt->plans[i], s);
+    if (e == hipSuccess) e = hipEventRecord(bt->last_use, s);
     return from_hip(e);
   } catch (...) {
     return BF_ERR_HIP;
@@ -864,8 +925,10 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
 
 int bf_batch_destroy(bf_batch_t bt) {
   if (!bt) return BF_OK;
-  (void)hipDeviceSynchronize();
-  if (bt->queue) (void)hipFree(bt->queue);
+  // the queue counter is released on the device after the batch's own last
+  // launch
+  (void)dev_release(bt->device, {bt->last_use}, {bt->queue});
+  if (bt->last_use) (void)hipEventDestroy(bt->last_use);
   delete bt;
   return BF_OK;
 }
@@ -875,7 +938,7 @@ int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, in
   try {
     if (!out) return BF_ERR_INVALID_ARG;
     *out = nullptr;
-    if (n_antennas < 1 || n_antennas > kMaxN || integration < 1) return BF_ERR_INVALID_ARG;
+    if (n_antennas < 1 || n_antennas > bf::kMaxN || integration < 1) return BF_ERR_INVALID_ARG;
     if (precision != BF_FP32 && precision != BF_FP16 && precision != BF_BF16)
       return BF_ERR_INVALID_ARG;
     if (flags & ~BF_INPUT_4BIT) return BF_ERR_INVALID_ARG;
@@ -885,12 +948,12 @@ int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, in
     t->I = integration;
     t->prec = precision;
     t->in4 = (flags & BF_INPUT_4BIT) != 0;
-    t->mode = mode_of(integration);
+    t->mode = bf::mode_of(integration);
     t->Kpad = 64 * ((2 * n_antennas + 63) / 64);
     // one LDS size for every launch: the largest batching variant that still
     // leaves two workgroups per CU (at least the smallest variant)
     t->lds = lds_bytes(precision, t->Kpad, 1);
-    for (const Tile& c : kMultiTiles) {
+    for (const Tile& c : bf::multi_tiles()) {
       const size_t l = lds_bytes(precision, t->Kpad, c.nbt);
       if (l <= 80 * 1024) t->lds = std::max(t->lds, l);
     }
@@ -901,8 +964,9 @@ int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, in
     hipError_t e = hipGetDevice(&t->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&t->n_cu, hipDeviceAttributeMultiprocessorCount,
                                                    t->device);
-    if (e == hipSuccess) e = hipMalloc((void**)&t->queue, sizeof(int32_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&t->table, sizeof(Launch));
+    if (e == hipSuccess) e = dev_alloc(t->device, (void**)&t->queue, 256);
+    if (e == hipSuccess) e = dev_alloc(t->device, (void**)&t->table, sizeof(Launch));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming);
     int occ = 0;
     if (e == hipSuccess) {
       Launch L;
@@ -911,8 +975,8 @@ int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, in
                                     &occ);
     }
     if (e != hipSuccess) {
-      if (t->queue) (void)hipFree(t->queue);
-      if (t->table) (void)hipFree(t->table);
+      if (t->last_use) (void)hipEventDestroy(t->last_use);
+      (void)dev_release(t->device, {}, {t->queue, t->table});
       delete t;
       return from_hip(e);
     }
@@ -947,7 +1011,10 @@ int bf_table_set(bf_table_t t, const bf_plan_t* plans, const int8_t* const* x, f
       if (st != BF_OK) return st;
     }
     L.queue = t->queue;
-    return from_hip(bf::launch_table_store(L, t->table, reinterpret_cast<hipStream_t>(stream)));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = bf::launch_table_store(L, t->table, s);
+    if (e == hipSuccess) e = record_unless_capturing(t->last_use, s);
+    return from_hip(e);
   } catch (...) {
     return BF_ERR_HIP;
   }
@@ -962,14 +1029,17 @@ int bf_table_run(bf_table_t t, void* stream) {
   if (e == hipSuccess)
     e = bf::launch_beamform_multi(t->prec, t->mode, t->in4, unused, t->table, t->grid, t->lds, s,
                                   nullptr);
+  if (e == hipSuccess) e = record_unless_capturing(t->last_use, s);
   return from_hip(e);
 }
 
 int bf_table_destroy(bf_table_t t) {
   if (!t) return BF_OK;
-  (void)hipDeviceSynchronize();
-  if (t->queue) (void)hipFree(t->queue);
-  if (t->table) (void)hipFree(t->table);
+  // released on the device after the table's own last store and uncaptured
+  // run (launches replayed from a captured graph are the caller's to wait
+  // for)
+  (void)dev_release(t->device, {t->last_use}, {t->queue, t->table});
+  if (t->last_use) (void)hipEventDestroy(t->last_use);
   delete t;
   return BF_OK;
 }

@@ -5,18 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bf_tiles.h"
+
 namespace bf {
-
-constexpr int kMaxProbs = 16;   // beam sets per launch (kernel-argument table)
-constexpr int kWaves = 4;       // waves per workgroup
-constexpr int kThreads = 64 * kWaves;
-constexpr int kChunk = 64;      // real K elements (32 antennas) per chunk
-constexpr int kLdsPad = 16;     // bytes added to each LDS weight row
-
-// Integration classes; each is a separate kernel instantiation:
-// I == 1, I == 2, I >= 3 with I % 4 != 0 (padded windows), I % 4 == 0;
-// and complex beam output (no detection, I == 1 row mapping).
-enum Mode : int { kModeI1 = 0, kModeI2 = 1, kModeGen = 2, kModeGen4 = 3, kModeCx = 4 };
 
 // One beam set (plan) inside a launch.  Lives in the kernel-argument
 // segment, so every field is read through scalar loads.
@@ -51,42 +42,6 @@ struct Launch {
   int32_t nprob;
   int32_t xcd_remap;  // non-persistent mode: group consecutive units per XCD
 };
-
-// Tile variant of the beamform kernel.
-struct Tile {
-  int mt;    // 16-row MFMA tiles per wave step
-  int nbt;   // 16-beam tiles per workgroup beam range
-  int nbp;   // 16-beam tiles per accumulator pass
-  int kres;  // K chunks held in registers per wave step (0: streamed)
-};
-
-// Compiled tile variants: (MT, NBT, NBP, KRES).  KRES > 0 variants serve
-// plans with Kpad / 64 <= KRES; KRES == 0 streams K with the unit's weights
-// in LDS; KRES < 0 streams K with the weights read from device memory (any
-// K: arrays whose weight rows do not fit LDS).  The generic (byte-load)
-// list serves plans whose 2N is not a multiple of 16.
-#define BF_TILE_LIST_VEC16                                                        \
-  BF_TILE(8, 8, 1, 1) BF_TILE(4, 8, 2, 1) BF_TILE(4, 8, 1, 1) BF_TILE(8, 4, 1, 1)  \
-  BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 1, 2) BF_TILE(4, 8, 2, 0)  \
-  BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 2, 1, 0) BF_TILE(4, 1, 1, 0)  \
-  BF_TILE(4, 2, 2, -1) BF_TILE(8, 1, 1, -1)
-#define BF_TILE_LIST_GENERIC BF_TILE(4, 8, 2, 0) BF_TILE(4, 1, 1, 0) BF_TILE(4, 2, 2, -1)
-// Variants compiled for 4-bit input.
-#define BF_TILE_LIST_IN4                                                          \
-  BF_TILE(4, 8, 1, 1) BF_TILE(4, 8, 2, 1) BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2)  \
-  BF_TILE(4, 8, 2, 0) BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0) BF_TILE(4, 1, 1, 0)  \
-  BF_TILE(4, 2, 2, -1)
-// Variants compiled for complex beam output (16-byte rows; byte-load plans
-// use the generic list).
-#define BF_TILE_LIST_CX                                                           \
-  BF_TILE(4, 8, 1, 1) BF_TILE(4, 4, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 8, 2, 0)  \
-  BF_TILE(4, 2, 2, 0) BF_TILE(4, 1, 1, 0) BF_TILE(4, 2, 2, -1)
-// Variants compiled into the persistent batching kernel (16-byte loads).
-// (MT = 8 variants are left out: their register use would halve the
-// kernel's occupancy for every set.)
-#define BF_TILE_LIST_MULTI                                                        \
-  BF_TILE(4, 8, 1, 1) BF_TILE(4, 8, 1, 2) BF_TILE(4, 4, 2, 0) BF_TILE(4, 2, 2, 0)  \
-  BF_TILE(4, 1, 1, 0)
 
 // Host-side launcher for one (precision, mode, vec16, input format, tile)
 // instantiation.  Returns hipSuccess or the launch error.
