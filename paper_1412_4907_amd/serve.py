@@ -23,8 +23,12 @@ builds those ideas on one MI355X:
   which ring slot, which output buffers) from device memory, so it is
   captured once as a hipGraph and replayed for every block; before each
   replay a one-workgroup kernel stores that block's table;
-* per block: arrival time, completion event, latency, and the real-time
-  factor (block period / processing time) are recorded.
+* per block: arrival time, completion time (stamped by a watcher thread as
+  soon as the block's completion event fires), latency, deadline misses
+  (completion later than arrival + one block period) and the real-time
+  factor (block period / processing time) are recorded;
+* a retired request's plan is freed once the last block that used it has
+  completed (its completion event), without synchronising the device.
 
 A request's output is bitwise the same whether it runs alone or in a mix
 (each work unit depends only on its own set's voltages and weights).
@@ -34,6 +38,8 @@ with a fake executor; ``GpuExecutor`` runs the C ABI.
 """
 from __future__ import annotations
 
+import queue
+import threading
 import time
 from dataclasses import dataclass
 from typing import Callable, Dict, List, Optional, Sequence
@@ -83,6 +89,42 @@ class BlockRecord:
     @property
     def latency_ms(self) -> float:
         return (self.done_s - self.arrival_s) * 1e3
+
+
+class CompletionWatcher:
+    """Stamps each block's completion time as soon as it completes: a thread
+    waits on the blocks' completion events in enqueue order (one stream
+    completes its work in order), so a block's stamp never waits for the
+    host's own pacing or ring-slot waits."""
+
+    def __init__(self, t0: float):
+        self.t0 = t0
+        self.q: "queue.Queue" = queue.Queue()
+        self.err: Optional[BaseException] = None
+        self.thread = threading.Thread(target=self._run, name="block-completion", daemon=True)
+        self.thread.start()
+
+    def add(self, ev, rec: "BlockRecord") -> None:
+        self.q.put((ev, rec))
+
+    def _run(self) -> None:
+        while True:
+            item = self.q.get()
+            if item is None:
+                return
+            ev, rec = item
+            try:
+                ev.synchronize()
+            except BaseException as e:  # reported by close()
+                self.err = e
+            rec.done_s = time.perf_counter() - self.t0
+
+    def close(self) -> None:
+        """Waits until every added block is stamped."""
+        self.q.put(None)
+        self.thread.join()
+        if self.err is not None:
+            raise self.err
 
 
 class Scheduler:
@@ -182,12 +224,13 @@ class GpuExecutor:
         self.outs: Dict[int, List] = {}
         self.table = bf.Table(self.N, self.I, precision, input_bits=input_bits)
         self.graph = None
-        self.graveyard: List = []
-        self.graveyard_outs: List = []
-        self.graveyard_held = 0
-        self.graveyard_bytes = 8 << 30
+        # retired requests whose last block may still be running:
+        # (that block's completion event, plan, outputs)
+        self.retiring: List = []
+        self.last_use: Dict[int, object] = {}
         self.eager_launches = 0
         self.graph_replays = 0
+        self.tuned_admissions = 0
 
     def admit(self, r: Request) -> None:
         torch = self.torch
@@ -198,30 +241,35 @@ class GpuExecutor:
             self.outs[r.rid] = [torch.empty((self.C, r.n_beams, self.T // self.I),
                                             dtype=torch.float32, device="cuda")
                                 for _ in range(2)]
-        self.tune.apply_cached(plan)
+        # the table kernel's own tuned tile for this shape (B bucketed), if
+        # the tile cache has one; else the plan keeps its creation tile
+        if plan.apply_tuned(batch=True):
+            self.tuned_admissions += 1
         self.plans[r.rid] = plan
 
     def retire(self, r: Request) -> None:
-        """Drop a request.  Freeing device memory synchronises the device,
-        so plans and outputs go to a graveyard that is emptied when it grows
-        past ``graveyard_bytes`` or at close(); a retired request is left out
-        of every later table."""
+        """Drop a request: it is left out of every later table, and its plan
+        and outputs are freed once the last block that read them has
+        completed (checked at every later block; never a device-wide
+        synchronisation)."""
         outs = self.outs.pop(r.rid, None)
         p = self.plans.pop(r.rid, None)
         if p is not None:
-            self.graveyard.append(p)
-            self.graveyard_held += sum(int(o.numel()) * 4 for o in (outs or []))
-            self.graveyard_outs.extend(outs or [])
-        if self.graveyard_held > self.graveyard_bytes:
-            self.flush_graveyard()
+            self.retiring.append((self.last_use.pop(r.rid, None), p, outs))
+        self.reap()
 
-    def flush_graveyard(self) -> None:
-        self.stream.synchronize()
-        for obj in self.graveyard:
-            obj.destroy()
-        self.graveyard.clear()
-        self.graveyard_outs.clear()
-        self.graveyard_held = 0
+    def reap(self, wait: bool = False) -> None:
+        """Free retired requests whose last block has completed (all of them,
+        waiting for each, if ``wait``)."""
+        keep = []
+        for ev, p, outs in self.retiring:
+            if ev is None or wait or ev.query():
+                if ev is not None:
+                    ev.synchronize()
+                p.destroy()  # waits only for the plan's own weight generation
+            else:
+                keep.append((ev, p, outs))
+        self.retiring = keep
 
     def run_block(self, ids: Sequence[int], slot: int, parity: int):
         """Enqueue one block's work on the serve stream; returns an event
@@ -259,6 +307,8 @@ class GpuExecutor:
         ev = torch.cuda.Event()
         ev.record(self.stream)
         self.slot_free[slot] = ev
+        for i in ids:
+            self.last_use[i] = ev
         return ev
 
     def output(self, rid: int, parity: int):
@@ -272,7 +322,7 @@ class GpuExecutor:
             p.destroy()
         self.plans.clear()
         self.outs.clear()
-        self.flush_graveyard()
+        self.reap(wait=True)
 
 
 def serve(executor, scheduler: Scheduler, requests: Sequence[Request], n_blocks: int,
@@ -283,13 +333,15 @@ def serve(executor, scheduler: Scheduler, requests: Sequence[Request], n_blocks:
     releases it at k * block_period_s / pace (a replay ``pace`` times faster
     than real time), and 0 releases each block as soon as its ring slot is
     free.  Returns one record per block (latency = release -> completion, so
-    a block that arrives while earlier ones still run includes its wait)."""
+    a block that arrives while earlier ones still run includes its wait); a
+    watcher thread stamps each completion when the block's event fires."""
     pending = sorted(requests, key=lambda r: r.arrival_block)
     pi = 0
     records: List[BlockRecord] = []
     inflight = []  # (event, record)
     n_slots = max(1, len(getattr(executor, "ring", [None])))
     t0 = time.perf_counter()
+    watcher = CompletionWatcher(t0)
     for k in range(n_blocks):
         while pi < len(pending) and pending[pi].arrival_block <= k:
             scheduler.submit(pending[pi])
@@ -306,7 +358,6 @@ def serve(executor, scheduler: Scheduler, requests: Sequence[Request], n_blocks:
         while len(inflight) >= n_slots:
             ev, rec = inflight.pop(0)
             ev.synchronize()
-            rec.done_s = time.perf_counter() - t0
         release = None
         if arrivals is not None:
             release = float(arrivals[k])
@@ -321,23 +372,31 @@ def serve(executor, scheduler: Scheduler, requests: Sequence[Request], n_blocks:
         rec = BlockRecord(k, sorted(scheduler.active), sum(r.n_beams for r in scheduler.active.values()),
                           arrived)
         ev = executor.run_block(rec.active, k % n_slots, k & 1)
+        watcher.add(ev, rec)
         inflight.append((ev, rec))
         records.append(rec)
         scheduler.block_done(k)
         if on_block is not None:
             on_block(k, rec)
-    for ev, rec in inflight:
-        ev.synchronize()
-        rec.done_s = time.perf_counter() - t0
+    watcher.close()
     for r in list(scheduler.active.values()):
         executor.retire(r)
     return records
 
 
-def summarize(records: Sequence[BlockRecord], block_period_s: float) -> dict:
+def summarize(records: Sequence[BlockRecord], block_period_s: float,
+              deadline_s: Optional[float] = None) -> dict:
+    """Throughput and latency of a run.  A block misses its deadline when it
+    completes later than ``deadline_s`` (default: one block period) after
+    its arrival, i.e. a real-time pipeline would have fallen behind."""
     lat = np.array([r.latency_ms for r in records])
     wall = records[-1].done_s - records[0].arrival_s if records else 0.0
+    dl_ms = (block_period_s if deadline_s is None else deadline_s) * 1e3
+    misses = int(np.count_nonzero(lat > dl_ms)) if len(lat) else 0
     return {"blocks": len(records),
+            "deadline_ms": dl_ms,
+            "deadline_misses": misses,
+            "deadline_miss_frac": (misses / len(records)) if records else 0.0,
             "rtf": (len(records) * block_period_s / wall) if wall > 0 else None,
             "p50_block_ms": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_block_ms": float(np.percentile(lat, 99)) if len(lat) else None,

@@ -1,7 +1,10 @@
-"""Serving-form scheduler on the CPU with a fake executor: admission by HBM
+"""Serving-form scheduler on the CPU with fake executors: admission by HBM
 footprint, retirement, cancellation, a failing request that does not stop
-the others, deadline accounting, and per-request results computed by the
-oracle on tiny shapes (alone == in the mix)."""
+the others, per-request results computed by the oracle on tiny shapes
+(alone == in the mix), block latency stamped at completion (not at the
+host's next wait), and deadline-miss accounting."""
+import time
+
 import numpy as np
 import pytest
 
@@ -139,3 +142,85 @@ def test_poisson_block_arrivals_release_and_latency():
         assert rec.arrival_s == pytest.approx(a)
         assert rec.done_s >= rec.arrival_s
     assert len(ex.launches) == 12
+
+
+class TimedEvent:
+    """Completes at a known host time (perf_counter seconds)."""
+
+    def __init__(self, done_at):
+        self.done_at = done_at
+
+    def query(self):
+        return time.perf_counter() >= self.done_at
+
+    def synchronize(self):
+        dt = self.done_at - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+
+
+class TimedExecutor:
+    """A device that runs blocks one after another, block k taking work_s[k]
+    seconds from when it is enqueued or the previous block ends."""
+
+    def __init__(self, work_s):
+        self.ring = [None, None]
+        self.work_s = list(work_s)
+        self.busy_until = 0.0
+        self.k = 0
+
+    def admit(self, r):
+        pass
+
+    def retire(self, r):
+        pass
+
+    def run_block(self, ids, slot, parity):
+        start = max(time.perf_counter(), self.busy_until)
+        self.busy_until = start + self.work_s[self.k]
+        self.k += 1
+        return TimedEvent(self.busy_until)
+
+
+def _timed_run(work_s, gap_s):
+    ex = TimedExecutor(work_s)
+    sch = serve.Scheduler(1 << 30, lambda r: 1)
+    reqs = [serve.Request(0, np.zeros((4, 3)), lifetime=None)]
+    arrivals = [gap_s * (k + 1) for k in range(len(work_s))]
+    recs = serve.serve(ex, sch, reqs, n_blocks=len(work_s), block_period_s=gap_s,
+                       arrivals=arrivals)
+    return recs
+
+
+def test_latency_is_completion_minus_arrival():
+    """A 5 ms block arriving every 50 ms has about 5 ms of latency: the
+    completion is stamped when the block ends, not when the host next waits
+    for its ring slot (which comes only after the next arrival)."""
+    recs = _timed_run([0.005] * 8, 0.05)
+    lat = np.array([r.latency_ms for r in recs])
+    assert np.all(lat >= 4.5), lat
+    assert np.median(lat) < 20.0, lat
+    st = serve.summarize(recs, 0.05)
+    assert st["deadline_misses"] == 0 and st["deadline_ms"] == pytest.approx(50.0)
+
+
+def test_deadline_misses_counted():
+    """One 120 ms block among 5 ms ones (50 ms period): it misses its
+    deadline, so does the next block (queued behind it), the one after
+    recovers."""
+    recs = _timed_run([0.005, 0.005, 0.120, 0.005, 0.005, 0.005], 0.05)
+    lat = [r.latency_ms for r in recs]
+    st = serve.summarize(recs, 0.05)
+    assert st["deadline_misses"] == 2, lat
+    assert lat[2] > 110 and lat[3] > 50 and lat[4] < 45, lat
+    assert st["deadline_miss_frac"] == pytest.approx(2 / 6)
+
+
+def test_summarize_deadline_from_records():
+    recs = [serve.BlockRecord(k, [0], 4, arrival_s=0.1 * k, done_s=0.1 * k + d)
+            for k, d in enumerate([0.01, 0.2, 0.05, 0.3])]
+    st = serve.summarize(recs, 0.1)
+    assert st["deadline_misses"] == 2
+    st = serve.summarize(recs, 0.1, deadline_s=0.25)
+    assert st["deadline_misses"] == 1
+    assert st["p50_block_ms"] == pytest.approx(125.0)
