@@ -87,24 +87,38 @@ def test_precision_forms(gpu, prec):
 
 # --- paper scale, full size, sampled channels ---------------------------------
 
-@pytest.mark.slow
-def test_paper_scale_sampled(gpu):
-    import torch
-    _announce("paper scale fp32 (4.29 GB input)")
+@pytest.fixture(scope="module")
+def paper_block():
+    """The paper-scale block (4.29 GB of int8 voltages), generated once."""
     w = synth.paper()
-    x = w.voltages(workers=16)
+    return w, w.voltages(workers=16)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_paper_scale_sampled(gpu, paper_block, prec):
+    """The bench's workload and launch: full block, the tile the tile cache
+    gives the plan at creation (the one bench.py times), five seeded
+    channels against the FP64 oracle."""
+    import torch
+    w, x = paper_block
     chans = [0, 511, 1023] + list(synth.rng("paper", "check").choice(1024, 2, replace=False))
-    with bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration) as plan:
+    with bf.Plan(w.n_ant, w.n_chan, w.n_beams, w.n_samples, w.integration, precision=prec) as plan:
+        info = plan.info()
+        _announce(f"paper scale {prec} (4.29 GB input), tile {plan.tile()} "
+                  f"tuned={info['tile_tuned']}")
+        assert info["tile_tuned"] == 1, "the tile cache has no entry for the paper block"
         plan.set_weights(w.pos, w.dirs, w.freqs)
         xd = torch.from_numpy(x).to(gpu)
-        p = torch.empty((w.n_chan, w.n_beams, w.n_samples // w.integration),
-                        dtype=torch.float32, device=gpu)
+        p = torch.full((w.n_chan, w.n_beams, w.n_samples // w.integration), float("nan"),
+                       dtype=torch.float32, device=gpu)
         plan.run(xd, p)
         torch.cuda.synchronize()
+        assert not bool(torch.isnan(p).any()), "some output was never written"
         got = p[chans].cpu().numpy()
         del xd, p
     ref = oracle.beamform(oracle.weights(w.pos, w.dirs, w.freqs[chans]), x[chans], w.integration)
-    st = assert_parity(got, ref, TOL["fp32"], "paper fp32")
+    st = assert_parity(got, ref, TOL[prec], f"paper {prec}")
     _announce(f"  {st}")
 
 
