@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--output", default="power", choices=["power", "complex"],
                     help="detected integrated power, or complex FP16 beams (integration 1)")
     ap.add_argument("--workload", default="paper",
-                    choices=["paper", "small", "precision", "serve", "batch", "tracking"])
+                    choices=["paper", "small", "precision", "large", "serve", "batch", "tracking"])
     ap.add_argument("--blocks", type=int, default=200, help="serve: blocks to stream")
     ap.add_argument("--pace", type=float, default=10.0,
                     help="serve: replay speed-up over real time for the latency run "
@@ -103,7 +103,8 @@ def copy_calibration(nbytes: int, reps: int = 3) -> None:
 
 def workload(name):
     from paper_1412_4907_amd import synth
-    return {"paper": synth.paper, "small": synth.small, "precision": synth.precision}[name]()
+    return {"paper": synth.paper, "small": synth.small, "precision": synth.precision,
+            "large": synth.large}[name]()
 
 
 def algorithmic_bytes(w, prec, output="power") -> float:

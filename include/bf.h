@@ -230,6 +230,7 @@ int bf_plan_set_antenna_mask(bf_plan_t plan, const uint8_t* mask);
 int bf_beam_pattern(bf_plan_t plan, const double* ant_xyz_m, const double* chan_freq_hz,
                     const double* grid_dir, int32_t n_dirs, float* p_dev, void* stream);
 
+
 /*
  * Load arbitrary complex weights (host [C][B][N][2] double, re/im), each
  * component rounded once to the storage precision.  Synchronous (returns
@@ -312,10 +313,11 @@ int bf_plan_set_output_scale(bf_plan_t plan, float scale);
  */
 int bf_plan_tile_candidates(bf_plan_t plan, int32_t* tiles, int32_t max_tiles);
 
-/* Free the plan.  Waits first for the plan's own outstanding device work --
- * weight generation, refreshes, and the bf_run / bf_batch_run /
- * bf_beam_pattern launches that read its weights -- through events the plan
- * records, never for other work on the device.  Launches of a bf_table that
+/* Free the plan.  Its device memory is released on the device only after
+ * the plan's own outstanding work -- weight generation, refreshes, and the
+ * bf_run / bf_batch_run / bf_beam_pattern launches that read its weights --
+ * has completed, through events the plan records; the call itself does not
+ * wait for that work, nor for any other work on the device.  Launches of a bf_table that
  * read the plan are not tracked by the plan: they must have completed (or
  * the table must hold another set) before the plan is destroyed.
  * NULL is accepted (no-op). */

@@ -338,6 +338,15 @@ def serve_block(block: int, n_chan: int = 1024, n_samples: int = 8192) -> Worklo
                     pos, np.zeros((0, 3)), channel_freqs(n_chan, 400e6, 16e6))
 
 
+def large(n_beams: int = 512) -> Workload:
+    """The serving form's block (256-antenna 16x16 grid, 1024 channels x 8192
+    samples, I=64, noise-only voltages) as a single plan of ``n_beams``
+    seeded directions within 25 deg of zenith."""
+    import dataclasses
+    dirs = random_dirs(n_beams, rng("serve", "tracking"), 25.0)
+    return dataclasses.replace(serve_block(0), name="large", n_beams=n_beams, dirs=dirs)
+
+
 def serve_block_arrivals(n_blocks: int, period_s: float, pace: float = 1.0) -> np.ndarray:
     """Seeded Poisson arrival times (seconds from the start) of the serving
     form's voltage blocks: exponential gaps with mean ``period_s / pace``

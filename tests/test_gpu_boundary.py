@@ -1,6 +1,6 @@
 """The C ABI's handle lifetime, argument checks and tile cache on the GPU:
-destroying a plan, batch or table waits for that handle's own device work
-only (never for another stream's), bf_run rejects overlapping voltage and
+destroying a plan, batch or table never waits for another stream's work, and
+a handle's memory outlives its own queued work; bf_run rejects overlapping voltage and
 output buffers, and plans take their tile from the loaded tile cache at
 creation (bf_tune_load, bf_tune_key, bf_plan_apply_tuned)."""
 import json
@@ -13,9 +13,9 @@ from paper_1412_4907_amd import bf, synth, tune
 pytestmark = pytest.mark.gpu
 
 
-def _busy_stream_work(torch, gpu, stream, runs=12):
-    """Enqueue about 0.2 s of beamforming on `stream` (a large FP32 plan run
-    repeatedly) and return (plan, event recorded after it)."""
+def _busy_plan(torch, gpu, stream):
+    """A large FP32 plan (about 16 ms per run) with its buffers, set up and
+    warmed on `stream` before any timing-sensitive check."""
     N, C, B, T, I = 32, 1024, 128, 65536, 16
     plan = bf.Plan(N, C, B, T, I)
     w = synth.paper()
@@ -23,11 +23,20 @@ def _busy_stream_work(torch, gpu, stream, runs=12):
     with torch.cuda.stream(stream):
         x = torch.randint(-128, 128, (C, T, N, 2), dtype=torch.int8, device=gpu)
         p = torch.empty((C, B, T // I), dtype=torch.float32, device=gpu)
+    plan.run(x, p, stream=stream)
+    stream.synchronize()
+    return plan, (x, p)
+
+
+def _busy_stream_work(torch, stream, plan, bufs, runs=24):
+    """Enqueue about 0.4 s of beamforming on `stream` and return the event
+    recorded after it.  Nothing here allocates, so no implicit device-wide
+    synchronisation can drain the stream early."""
     for _ in range(runs):
-        plan.run(x, p, stream=stream)
+        plan.run(*bufs, stream=stream)
     ev = torch.cuda.Event()
     ev.record(stream)
-    return plan, ev, (x, p)
+    return ev
 
 
 def _small(gpu, torch, stream):
@@ -43,49 +52,67 @@ def _small(gpu, torch, stream):
 
 
 def test_destroy_does_not_wait_for_other_streams(gpu):
+    """Handles whose own work has completed are destroyed while about 0.4 s
+    of another stream's work is queued: every destroy returns with that work
+    still pending.  (The handles' own runs finish before the other work is
+    enqueued, since two streams may share one hardware queue.)"""
     import torch
     print("destroy vs another stream's work", flush=True)
     busy, own = torch.cuda.Stream(), torch.cuda.Stream()
-    big, busy_done, keep = _busy_stream_work(torch, gpu, busy)
+    big, bufs = _busy_plan(torch, gpu, busy)
     plan, x, p = _small(gpu, torch, own)
-    plan.run(x, p, stream=own)
-    own.synchronize()
-    assert not busy_done.query(), "the busy stream finished too early for this check"
-    plan.destroy()
-    # the plan's own work was complete; destroy must not have drained `busy`
-    assert not busy_done.query(), "bf_plan_destroy waited for another stream's work"
-    # batch and table handles likewise
     p2, x2, o2 = _small(gpu, torch, own)
     batch = bf.Batch([p2])
-    batch.run([x2], [o2], stream=own)
     tab = bf.Table(16, 4, "fp16")
     tab.set([p2], [x2], [o2], stream=own)
+    plan.run(x, p, stream=own)
+    batch.run([x2], [o2], stream=own)
     tab.run(stream=own)
-    own.synchronize()
+    torch.cuda.synchronize()
+
+    busy_done = _busy_stream_work(torch, busy, big, bufs)
+    plan.destroy()
+    assert not busy_done.query(), "bf_plan_destroy waited for another stream's work"
     batch.destroy()
     tab.destroy()
     p2.destroy()
     assert not busy_done.query(), "a batch or table destroy waited for another stream's work"
     torch.cuda.synchronize()
     big.destroy()
-    del keep
+    del bufs
 
 
-def test_destroy_waits_for_own_work(gpu):
+def test_destroy_keeps_memory_until_own_work_is_done(gpu):
+    """A plan destroyed while its run is still queued: the run must still read
+    the plan's weights, so its output equals the same run made earlier, even
+    though a new plan of the same size is created and given other weights
+    before that run executes."""
     import torch
-    print("destroy waits for the plan's own queued run", flush=True)
-    busy = torch.cuda.Stream()
-    big, busy_done, keep = _busy_stream_work(torch, gpu, busy)
+    print("destroy with the plan's own run still queued", flush=True)
+    busy, side = torch.cuda.Stream(), torch.cuda.Stream()
+    big, bufs = _busy_plan(torch, gpu, busy)
     plan, x, p = _small(gpu, torch, busy)
+    plan.run(x, p, stream=busy)
+    torch.cuda.synchronize()
+    ref = p.cpu().numpy()
+    p.fill_(float("nan"))
+    torch.cuda.synchronize()
+    _busy_stream_work(torch, busy, big, bufs)
     plan.run(x, p, stream=busy)  # queued behind the long work
     ran = torch.cuda.Event()
     ran.record(busy)
     assert not ran.query()
     plan.destroy()
-    assert ran.query(), "bf_plan_destroy returned before the plan's own run completed"
+    other, _, _ = _small(gpu, torch, side)
+    g = np.random.default_rng(9)
+    other.set_weights(synth.disc_positions(16, 50.0, g), synth.random_dirs(20, g),
+                      np.linspace(401e6, 409e6, 4), stream=side)
+    side.synchronize()
     torch.cuda.synchronize()
+    assert np.array_equal(p.cpu().numpy(), ref), "the destroyed plan's queued run lost its weights"
+    other.destroy()
     big.destroy()
-    del keep
+    del bufs
 
 
 def test_run_rejects_overlapping_buffers(gpu):
