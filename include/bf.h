@@ -230,6 +230,22 @@ int bf_plan_set_antenna_mask(bf_plan_t plan, const uint8_t* mask);
 int bf_beam_pattern(bf_plan_t plan, const double* ant_xyz_m, const double* chan_freq_hz,
                     const double* grid_dir, int32_t n_dirs, float* p_dev, void* stream);
 
+/*
+ * bf_beam_pattern for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation): the
+ * same map, computed by the same kernel, but the geometry is staged in a
+ * fixed array the library holds on each GPU for the life of the process
+ * (2^20 doubles, 8 MiB per device) instead of a buffer allocated per call.
+ * It calls no allocator and does not wait: the three host arrays are copied
+ * on `stream` before return (the caller may reuse them at once), and the map
+ * is complete when `stream` reaches this point.  Arguments, layout and the
+ * other errors as for bf_beam_pattern; BF_ERR_INVALID_ARG also when
+ * 3 N + C + 3 n_dirs exceeds 2^20.  Every call on a GPU shares that GPU's
+ * array: calls on one stream are ordered, calls on different streams of one
+ * GPU that overlap in time race for it and must be serialised by the caller.
+ */
+int bf_beam_pattern_noalloc(bf_plan_t plan, const double* ant_xyz_m, const double* chan_freq_hz,
+                            const double* grid_dir, int32_t n_dirs, float* p_dev, void* stream);
 
 /*
  * Load arbitrary complex weights (host [C][B][N][2] double, re/im), each

@@ -33,7 +33,11 @@ EXPORTS = ["bf_strerror", "bf_version", "bf_last_hip_error", "bf_tune_load", "bf
            "bf_plan_tile_candidates",
            "bf_plan_destroy", "bf_batch_create", "bf_batch_tile_candidates", "bf_batch_run",
            "bf_batch_destroy", "bf_table_create", "bf_table_set", "bf_table_run",
-           "bf_table_destroy"]
+           "bf_table_destroy", "bf_beam_pattern_noalloc"]
+
+# capacity of the allocation-free beam-pattern entry point's geometry staging,
+# in doubles: 3 N + C + 3 G must not exceed it
+PATTERN_SCRATCH_DOUBLES = 1 << 20
 
 
 class BfError(RuntimeError):
@@ -86,6 +90,7 @@ def lib() -> ctypes.CDLL:
         L.bf_set_weights_async.argtypes = [P, P, P, P, P]
         L.bf_plan_set_antenna_mask.argtypes = [P, P]
         L.bf_beam_pattern.argtypes = [P, P, P, P, i32, P, P]
+        L.bf_beam_pattern_noalloc.argtypes = [P, P, P, P, i32, P, P]
         L.bf_set_weights_raw.argtypes = [P, P, P]
         L.bf_get_weights.argtypes = [P, P, P]
         L.bf_run.argtypes = [P, P, P, P]
@@ -234,9 +239,11 @@ class Plan:
                                           freqs.ctypes.data, _stream_ptr(stream)),
                "bf_set_weights_async")
 
-    def beam_pattern(self, pos, freqs, grid_dirs, out=None, stream=None):
+    def beam_pattern(self, pos, freqs, grid_dirs, out=None, stream=None, noalloc=False):
         """Power of every beam for a unit plane wave from each grid direction:
-        float32 [C][B][G] device tensor (``bf_beam_pattern``)."""
+        float32 [C][B][G] device tensor (``bf_beam_pattern``; with ``noalloc``
+        ``bf_beam_pattern_noalloc``, which stages the geometry in the
+        library's fixed per-device array and returns without waiting)."""
         import torch
         pos = _host_f64(pos, (self.N, 3))
         freqs = _host_f64(freqs, (self.C,))
@@ -247,9 +254,10 @@ class Plan:
         if out.dtype != torch.float32 or tuple(out.shape) != (self.C, self.B, G) or \
                 not out.is_cuda or not out.is_contiguous():
             raise ValueError(f"out must be a contiguous float32 device tensor [{self.C}][{self.B}][{G}]")
-        _check(lib().bf_beam_pattern(self.handle, pos.ctypes.data, freqs.ctypes.data,
-                                     gd.ctypes.data, G, out.data_ptr(), _stream_ptr(stream)),
-               "bf_beam_pattern")
+        name = "bf_beam_pattern_noalloc" if noalloc else "bf_beam_pattern"
+        _check(getattr(lib(), name)(self.handle, pos.ctypes.data, freqs.ctypes.data,
+                                    gd.ctypes.data, G, out.data_ptr(), _stream_ptr(stream)),
+               name)
         return out
 
     def set_antenna_mask(self, mask=None) -> None:

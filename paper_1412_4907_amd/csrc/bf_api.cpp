@@ -623,24 +623,32 @@ int bf_set_weights_async(bf_plan_t p, const double* pos, const double* dir, cons
   }
 }
 
+// Arguments of the beam-pattern entry points.
+static int pattern_args(const bf_plan_s* p, const double* pos, const double* freq,
+                 const double* grid_dir, int32_t n_dirs, const float* p_dev) {
+  if (!p || !pos || !freq || !grid_dir || !p_dev || n_dirs < 1 || n_dirs > (1 << 24) ||
+      ((uintptr_t)p_dev & 3u) != 0)
+    return BF_ERR_INVALID_ARG;
+  if (!p->weights_set && !p->refresh_pending) return BF_ERR_STATE;
+  for (int64_t i = 0; i < 3 * (int64_t)p->N; ++i)
+    if (!std::isfinite(pos[i])) return BF_ERR_INVALID_ARG;
+  for (int c = 0; c < p->C; ++c)
+    if (!std::isfinite(freq[c]) || !(freq[c] > 0.0)) return BF_ERR_INVALID_ARG;
+  for (int g = 0; g < n_dirs; ++g) {
+    const double* d = grid_dir + 3 * (int64_t)g;
+    if (!std::isfinite(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2]))
+      return BF_ERR_INVALID_ARG;
+    if (std::fabs(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) > 1e-9)
+      return BF_ERR_INVALID_ARG;
+  }
+  return BF_OK;
+}
+
 int bf_beam_pattern(bf_plan_t p, const double* pos, const double* freq, const double* grid_dir,
                     int32_t n_dirs, float* p_dev, void* stream) {
   try {
-    if (!p || !pos || !freq || !grid_dir || !p_dev || n_dirs < 1 || n_dirs > (1 << 24) ||
-        ((uintptr_t)p_dev & 3u) != 0)
-      return BF_ERR_INVALID_ARG;
-    if (!p->weights_set && !p->refresh_pending) return BF_ERR_STATE;
-    for (int64_t i = 0; i < 3 * (int64_t)p->N; ++i)
-      if (!std::isfinite(pos[i])) return BF_ERR_INVALID_ARG;
-    for (int c = 0; c < p->C; ++c)
-      if (!std::isfinite(freq[c]) || !(freq[c] > 0.0)) return BF_ERR_INVALID_ARG;
-    for (int g = 0; g < n_dirs; ++g) {
-      const double* d = grid_dir + 3 * (int64_t)g;
-      if (!std::isfinite(d[0]) || !std::isfinite(d[1]) || !std::isfinite(d[2]))
-        return BF_ERR_INVALID_ARG;
-      if (std::fabs(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) - 1.0) > 1e-9)
-        return BF_ERR_INVALID_ARG;
-    }
+    const int st = pattern_args(p, pos, freq, grid_dir, n_dirs, p_dev);
+    if (st != BF_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = take_refresh(p, s);
     if (e != hipSuccess) return from_hip(e);
@@ -661,6 +669,47 @@ int bf_beam_pattern(bf_plan_t p, const double* pos, const double* freq, const do
     (void)hipFree(d);
     if (e != hipSuccess) return from_hip(e);
     return from_hip(e2);
+  } catch (...) {
+    return BF_ERR_HIP;
+  }
+}
+
+int bf_beam_pattern_noalloc(bf_plan_t p, const double* pos, const double* freq,
+                            const double* grid_dir, int32_t n_dirs, float* p_dev, void* stream) {
+  try {
+    const int st = pattern_args(p, pos, freq, grid_dir, n_dirs, p_dev);
+    if (st != BF_OK) return st;
+    const size_t nd = (size_t)3 * p->N + (size_t)p->C + (size_t)3 * n_dirs;
+    if (nd > bf::kPatScratchDoubles) return BF_ERR_INVALID_ARG;
+    // the staging array's address on the plan's device, looked up with that
+    // device current
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return from_hip(e);
+    if (cur != p->device) e = hipSetDevice(p->device);
+    double* d = nullptr;
+    if (e == hipSuccess) e = bf::pattern_scratch(p->device, &d);
+    if (cur != p->device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return from_hip(e);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    e = take_refresh(p, s);
+    // stream-ordered copies: a previous call's map on this stream has read
+    // the array before it is overwritten (calls on other streams race)
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d, pos, sizeof(double) * 3 * p->N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d + 3 * p->N, freq, sizeof(double) * p->C, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d + 3 * p->N + p->C, grid_dir, sizeof(double) * 3 * (size_t)n_dirs,
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = bf::launch_beam_pattern(p->prec, p->w_dev, d, d + 3 * p->N + p->C, d + 3 * p->N,
+                                  p->N, p->C, p->B, p->Bpad, p->Kpad, n_dirs, p_dev, s);
+    if (e == hipSuccess) e = mark_used(p, s);
+    return from_hip(e);
   } catch (...) {
     return BF_ERR_HIP;
   }

@@ -59,6 +59,11 @@ hipError_t launch_beamform_multi(int prec, int mode, bool in4, const Launch& L,
 hipError_t launch_beam_pattern(int prec, const void* w, const double* pos, const double* gdir,
                                const double* freq, int N, int C, int B, int Bpad, int Kpad, int G,
                                float* out, hipStream_t stream);
+// Capacity, in doubles, of the beam-pattern geometry staging array that the
+// allocation-free entry point uses (3N + C + 3G values per call).
+constexpr size_t kPatScratchDoubles = (size_t)1 << 20;
+// Device address of that array on device `dev`, which must be current.
+hipError_t pattern_scratch(int dev, double** out);
 
 // mask: device [N], 0 drops an antenna (every weight of it is zero).
 hipError_t launch_weights_geom(int prec, const double* pos, const double* dir,

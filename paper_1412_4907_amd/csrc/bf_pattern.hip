@@ -13,6 +13,8 @@
 // and the sums are FP32.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "bf_internal.h"
 
 namespace bf {
@@ -118,6 +120,32 @@ __global__ void __launch_bounds__(256) pattern_kernel(const void* __restrict__ w
 }
 
 }  // namespace
+
+// Geometry staging of the allocation-free entry point: antenna positions,
+// channel frequencies and grid directions (FP64) of one call, at most
+// kPatScratchDoubles values.  Each GPU the library runs on holds its own
+// copy until the process ends, and every call on that GPU shares it.
+static __device__ __align__(256) double scratch[kPatScratchDoubles];
+
+// Device address of `scratch` on device `dev` (made current by the caller),
+// looked up once per device.  The array's name is a host-side stand-in in
+// host code; only this address may reach kernels or copies.
+hipError_t pattern_scratch(int dev, double** out) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDev] = {};
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(ptr);
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_beam_pattern(int prec, const void* w, const double* pos, const double* gdir,
                                const double* freq, int N, int C, int B, int Bpad, int Kpad, int G,
