@@ -52,7 +52,9 @@ def _compile(src: str, verbose: bool, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if not force and not _stale(src, obj):
         return obj
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    # the device assembly is kept next to the object (-save-temps=obj) for
+    # the SrcC hazard check that follows the build
+    cmd = [HIPCC] + FLAGS + ["-save-temps=obj", "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, "-x", "hip"] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
@@ -74,8 +76,37 @@ def build(verbose: bool = False, force: bool = True) -> str:
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+    check_hazards(verbose)
     os.replace(LIB + ".tmp", LIB)
     return LIB
+
+
+# Kernels whose built code must pass the SrcC hazard check (isa_check.py);
+# the build fails if one of them does not.  Other kernels are reported.
+ENFORCED = ("beamform_",)
+
+
+def check_hazards(verbose: bool = False) -> dict:
+    """Run the SrcC hazard check over the device assembly of this build;
+    raise if an enforced kernel fails it.  Returns {kernel: violations}."""
+    import glob
+    try:
+        from . import isa_check
+    except ImportError:  # run as a script
+        sys.path.insert(0, HERE)
+        import isa_check
+    files = sorted(glob.glob(os.path.join(BUILD, "*-hip-amdgcn-amd-amdhsa-gfx950.s")))
+    if not files:
+        raise RuntimeError("no device assembly found for the hazard check")
+    bad = isa_check.check_files(files)
+    enforced = {k: v for k, v in bad.items() if any(e in k for e in ENFORCED)}
+    if verbose or enforced:
+        for k, v in bad.items():
+            print(f"hazard check: {k.rsplit(':', 1)[-1][:90]}: {len(v)} SrcC rewrites "
+                  f"within {isa_check.WAIT} wait states", flush=True)
+    if enforced:
+        raise RuntimeError(f"SrcC hazard check failed for {len(enforced)} enforced kernels")
+    return bad
 
 
 def source_hash() -> str:

@@ -62,6 +62,7 @@ struct bf_table_s {
   int32_t N = 0, I = 0;
   int prec = 0, mode = 0;
   bool in4 = false;
+  bool wide = false;  // every set runs the eight-wave streamed form
   int32_t Kpad = 0;
   size_t lds = 0;     // fixed dynamic LDS of every launch
   int grid = 1;       // fixed persistent grid: CUs x workgroups per CU
@@ -108,7 +109,8 @@ Prob make_prob(const bf_plan_s* p, const int8_t* x, float* out, int64_t unit_beg
   q.SG = SG;
   q.sgw = p->sgw;
   q.nbr = (p->Bpad / 16 + p->tile.nbt - 1) / p->tile.nbt;
-  q.ntr = (int32_t)((SG + (int64_t)bf::kWaves * p->sgw - 1) / ((int64_t)bf::kWaves * p->sgw));
+  const int64_t per = (int64_t)bf::waves_of(p->tile) * p->sgw;  // store groups per unit
+  q.ntr = (int32_t)((SG + per - 1) / per);
   q.accumulate = (p->flags & BF_ACCUMULATE) ? 1 : 0;
   q.variant = -1;
   // several beam ranges per channel: a time range's voltage rows (its
@@ -254,7 +256,7 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // fits lds_cap), unit ranges and the largest LDS size any set needs.
 // Byte-load sets (2N % 16 != 0) share one generic variant (*common).
 int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* const* out,
-              size_t lds_cap, Launch* L, size_t* lds_out, Tile* common) {
+              size_t lds_cap, Launch* L, size_t* lds_out, Tile* common, bool wide = false) {
   std::memset(L, 0, sizeof(*L));
   for (int i = 0; i < n; ++i) {
     const bf_plan_s* p = plans[i];
@@ -295,7 +297,20 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
     bf_plan_s tmp = *plans[i];  // the same set under its launch tile
     Tile t = *common;
     int variant = -1;
-    if (multi) {
+    if (wide) {
+      // the widest eight-wave beam range whose weights fit the launch's LDS
+      // and that the set's beams fill beyond one narrower range
+      const std::vector<Tile> kWide = bf::wide_tiles();
+      for (int v = 0; v < (int)kWide.size() && variant < 0; ++v) {
+        const Tile& c = kWide[v];
+        const bool last = v + 1 == (int)kWide.size();
+        if (tile_ok(tmp, c) && lds_bytes(tmp.prec, tmp.Kpad, c.nbt) <= lds_cap &&
+            (last || tmp.Bpad / 16 > c.nbt / 2))
+          variant = v;
+      }
+      if (variant < 0) return BF_ERR_UNSUPPORTED;
+      t = kWide[variant];
+    } else if (multi) {
       const std::vector<Tile> kMultiTiles = bf::multi_tiles();
       const int nm = (int)kMultiTiles.size();
       auto fits = [&](const Tile& c) {
@@ -999,12 +1014,28 @@ int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, in
     t->in4 = (flags & BF_INPUT_4BIT) != 0;
     t->mode = bf::mode_of(integration);
     t->Kpad = 64 * ((2 * n_antennas + 63) / 64);
-    // one LDS size for every launch: the largest batching variant that still
-    // leaves two workgroups per CU (at least the smallest variant)
-    t->lds = lds_bytes(precision, t->Kpad, 1);
-    for (const Tile& c : bf::multi_tiles()) {
-      const size_t l = lds_bytes(precision, t->Kpad, c.nbt);
-      if (l <= 80 * 1024) t->lds = std::max(t->lds, l);
+    // Arrays whose K needs more than two 64-wide chunks (where the four-wave
+    // kernel streams K) run every set in the eight-wave streamed form, FP16
+    // and BF16 with I == 1 or I % 4 == 0; its LDS holds the widest beam
+    // range that fits.  Otherwise one LDS size for every launch: the largest
+    // four-wave batching variant that still leaves two workgroups per CU (at
+    // least the smallest variant).
+    t->wide = precision != BF_FP32 && (t->mode == bf::kModeI1 || t->mode == bf::kModeGen4) &&
+              t->Kpad > 2 * bf::kChunk;
+    if (t->wide) {
+      t->lds = 0;
+      for (const Tile& c : bf::wide_tiles()) {
+        const size_t l = lds_bytes(precision, t->Kpad, c.nbt);
+        if (l <= kLdsMax) t->lds = std::max(t->lds, l);
+      }
+      if (t->lds == 0) t->wide = false;
+    }
+    if (!t->wide) {
+      t->lds = lds_bytes(precision, t->Kpad, 1);
+      for (const Tile& c : bf::multi_tiles()) {
+        const size_t l = lds_bytes(precision, t->Kpad, c.nbt);
+        if (l <= 80 * 1024) t->lds = std::max(t->lds, l);
+      }
     }
     if (t->lds > kLdsMax) {
       delete t;
@@ -1021,7 +1052,7 @@ int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, in
       Launch L;
       std::memset(&L, 0, sizeof(L));
       e = bf::launch_beamform_multi(precision, t->mode, t->in4, L, t->table, 0, t->lds, nullptr,
-                                    &occ);
+                                    &occ, t->wide);
     }
     if (e != hipSuccess) {
       if (t->last_use) (void)hipEventDestroy(t->last_use);
@@ -1056,7 +1087,7 @@ int bf_table_set(bf_table_t t, const bf_plan_t* plans, const int8_t* const* x, f
     if (n > 0) {
       size_t lds = 0;
       Tile common{4, 1, 1, 0};
-      const int st = fill_sets(plans, n, x, out, t->lds, &L, &lds, &common);
+      const int st = fill_sets(plans, n, x, out, t->lds, &L, &lds, &common, t->wide);
       if (st != BF_OK) return st;
     }
     L.queue = t->queue;
@@ -1077,7 +1108,7 @@ int bf_table_run(bf_table_t t, void* stream) {
   hipError_t e = bf::launch_queue_reset(t->queue, s);
   if (e == hipSuccess)
     e = bf::launch_beamform_multi(t->prec, t->mode, t->in4, unused, t->table, t->grid, t->lds, s,
-                                  nullptr);
+                                  nullptr, t->wide);
   if (e == hipSuccess) e = record_unless_capturing(t->last_use, s);
   return from_hip(e);
 }
@@ -1102,12 +1133,12 @@ hipError_t launch_prec_in(int mode, bool vec16, Tile t, const Launch& L, int gri
                           hipStream_t s);
 template <int PREC, bool IN4>
 hipError_t launch_multi_in(int mode, const Launch& L, const Launch* table, int grid, size_t lds,
-                           hipStream_t s, int* occupancy);
+                           hipStream_t s, int* occupancy, bool wide);
 #define BF_EXTERN(P, F)                                                                     \
   extern template hipError_t launch_prec_in<P, F>(int, bool, Tile, const Launch&, int, size_t, \
                                                   hipStream_t);                              \
   extern template hipError_t launch_multi_in<P, F>(int, const Launch&, const Launch*, int,    \
-                                                   size_t, hipStream_t, int*);
+                                                   size_t, hipStream_t, int*, bool);
 BF_EXTERN(0, false)
 BF_EXTERN(1, false)
 BF_EXTERN(2, false)
@@ -1118,15 +1149,15 @@ BF_EXTERN(2, true)
 
 hipError_t launch_beamform_multi(int prec, int mode, bool in4, const Launch& L,
                                  const Launch* table, int grid, size_t lds, hipStream_t s,
-                                 int* occ) {
+                                 int* occ, bool wide) {
   if (in4) {
-    if (prec == 0) return launch_multi_in<0, true>(mode, L, table, grid, lds, s, occ);
-    if (prec == 1) return launch_multi_in<1, true>(mode, L, table, grid, lds, s, occ);
-    return launch_multi_in<2, true>(mode, L, table, grid, lds, s, occ);
+    if (prec == 0) return launch_multi_in<0, true>(mode, L, table, grid, lds, s, occ, wide);
+    if (prec == 1) return launch_multi_in<1, true>(mode, L, table, grid, lds, s, occ, wide);
+    return launch_multi_in<2, true>(mode, L, table, grid, lds, s, occ, wide);
   }
-  if (prec == 0) return launch_multi_in<0, false>(mode, L, table, grid, lds, s, occ);
-  if (prec == 1) return launch_multi_in<1, false>(mode, L, table, grid, lds, s, occ);
-  return launch_multi_in<2, false>(mode, L, table, grid, lds, s, occ);
+  if (prec == 0) return launch_multi_in<0, false>(mode, L, table, grid, lds, s, occ, wide);
+  if (prec == 1) return launch_multi_in<1, false>(mode, L, table, grid, lds, s, occ, wide);
+  return launch_multi_in<2, false>(mode, L, table, grid, lds, s, occ, wide);
 }
 
 hipError_t launch_beamform(int prec, int mode, bool vec16, bool in4, Tile tile, const Launch& L,

@@ -6,5 +6,5 @@ namespace bf {
 template hipError_t launch_prec_in<1, true>(int, bool, Tile, const Launch&, int, size_t,
                                              hipStream_t);
 template hipError_t launch_multi_in<1, true>(int, const Launch&, const Launch*, int, size_t,
-                                              hipStream_t, int*);
+                                              hipStream_t, int*, bool);
 }

@@ -31,6 +31,11 @@ const Tile kIn4Tiles[] = {
     BF_TILE_LIST_IN4
 #undef BF_TILE
 };
+const Tile kWideTiles[] = {
+#define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
+    BF_TILE_LIST_WIDE
+#undef BF_TILE
+};
 const Tile kCxTiles[] = {
 #define BF_TILE(MT, NBT, NBP, KRES) Tile{MT, NBT, NBP, KRES},
     BF_TILE_LIST_CX
@@ -95,7 +100,7 @@ size_t lds_bytes(int prec, int32_t Kpad, int nbt) {
 }
 
 size_t tile_lds(int prec, int32_t Kpad, Tile t) {
-  return t.kres < 0 ? 0 : lds_bytes(prec, Kpad, t.nbt);
+  return t.kres == -1 ? 0 : lds_bytes(prec, Kpad, t.nbt);
 }
 
 void schedule(int32_t I, int64_t T, int32_t* G, int32_t* QI, int32_t* SG) {
@@ -117,14 +122,39 @@ bool same_tile(const Tile& a, const Tile& b) {
   return a.mt == b.mt && a.nbt == b.nbt && a.nbp == b.nbp && a.kres == b.kres;
 }
 
+// The eight-wave form's conditions: FP16/BF16 power output, 16-byte rows,
+// I == 1 or I % 4 == 0 (I % MT == 0 is checked per tile), overwriting
+// output, whole 16-byte window quads (T / I % 4 == 0), and byte offsets
+// within one channel's voltages (rows up to the last store group's padding,
+// plus the out-of-range marker 2^31 added to them) and one channel's output
+// rows that fit the 32-bit buffer offsets it uses.
+static bool wide_shape(const Shape& s) {
+  if (s.prec == BF_FP32 || s.cx || !s.vec16 || (s.flags & BF_ACCUMULATE)) return false;
+  if (s.mode != kModeI1 && s.mode != kModeGen4) return false;
+  const int64_t W = s.T / s.I;
+  if (W % 4 != 0) return false;
+  const int64_t rowb = s.in4 ? s.N : 2 * (int64_t)s.N;
+  return (s.T + 16 * (int64_t)s.I) * rowb < 0x7FFFFFFF && (int64_t)s.B * W * 4 < 0x7FFFFFFF;
+}
+
 std::vector<Tile> compiled_tiles(const Shape& s) {
-  if (s.cx && s.vec16) return as_vector(kCxTiles);
-  if (s.in4) return as_vector(kIn4Tiles);
-  if (s.vec16) return as_vector(kVecTiles);
-  return as_vector(kGenTiles);
+  std::vector<Tile> v;
+  if (s.cx && s.vec16)
+    v = as_vector(kCxTiles);
+  else if (s.in4)
+    v = as_vector(kIn4Tiles);
+  else if (s.vec16)
+    v = as_vector(kVecTiles);
+  else
+    v = as_vector(kGenTiles);
+  if (wide_shape(s))
+    for (const Tile& t : kWideTiles) v.push_back(t);
+  return v;
 }
 
 std::vector<Tile> multi_tiles() { return as_vector(kMultiTiles); }
+
+std::vector<Tile> wide_tiles() { return as_vector(kWideTiles); }
 
 bool tile_exists(const Shape& s, Tile t) {
   for (const Tile& x : compiled_tiles(s))
@@ -135,6 +165,7 @@ bool tile_exists(const Shape& s, Tile t) {
 bool tile_ok(const Shape& s, Tile t) {
   if (!tile_exists(s, t)) return false;
   if (t.kres > 0 && s.Kpad / kChunk > t.kres) return false;
+  if (t.kres == kKresWide && s.mode == kModeGen4 && s.I % t.mt != 0) return false;
   return tile_lds(s.prec, s.Kpad, t) <= kLdsMax;
 }
 
@@ -142,7 +173,7 @@ int64_t units_for(const Shape& s, Tile t, int32_t sgw) {
   int32_t G, QI, SG;
   schedule(s.I, s.T, &G, &QI, &SG);
   const int64_t nbr = (s.Bpad / 16 + t.nbt - 1) / t.nbt;
-  const int64_t per = (int64_t)kWaves * sgw;
+  const int64_t per = (int64_t)waves_of(t) * sgw;
   const int64_t ntr = (SG + per - 1) / per;
   return (int64_t)s.C * nbr * ntr;
 }
@@ -184,7 +215,7 @@ void choose_tile(const Shape& s, Tile* out, int32_t* out_sgw) {
   for (int32_t k = 2;; ++k) {
     const int32_t v = base * k;
     if ((int64_t)v * G > 256 || units_for(s, t, v) < want) break;
-    if ((int64_t)(v - base) * kWaves >= SG) break;
+    if ((int64_t)(v - base) * waves_of(t) >= SG) break;
     sgw = v;
   }
   *out = t;

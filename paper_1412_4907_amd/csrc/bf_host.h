@@ -71,6 +71,8 @@ int check_tile(const Shape& s, Tile t, int32_t sgw);
 std::vector<Tile> compiled_tiles(const Shape& s);
 // The variants the persistent batching kernel carries.
 std::vector<Tile> multi_tiles();
+// Variants of the eight-wave batching kernels (BF_TILE_LIST_WIDE order).
+std::vector<Tile> wide_tiles();
 
 // Bytes of one block of voltages, and of one run's output.
 uint64_t input_bytes(const Shape& s);

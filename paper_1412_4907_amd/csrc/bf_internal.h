@@ -49,10 +49,12 @@ hipError_t launch_beamform(int prec, int mode, bool vec16, bool in4, Tile tile, 
                            int grid, size_t lds_bytes, hipStream_t stream);
 // Persistent batching kernel (per-set variants).  table != null: the form
 // that reads its set table from that device copy (L unused).
-// occupancy != null only queries workgroups per CU.
+// occupancy != null only queries workgroups per CU.  wide: the eight-wave
+// kernels (FP16/BF16, I == 1 or I % 4 == 0; variants index
+// BF_TILE_LIST_WIDE) instead of the four-wave ones (BF_TILE_LIST_MULTI).
 hipError_t launch_beamform_multi(int prec, int mode, bool in4, const Launch& L,
                                  const Launch* table, int grid, size_t lds_bytes,
-                                 hipStream_t stream, int* occupancy);
+                                 hipStream_t stream, int* occupancy, bool wide = false);
 
 // Beam-pattern map: P[c][b][g] over G grid directions (device pos [N][3],
 // gdir [G][3], freq [C]; weights in the plan's operand layout).

@@ -4,7 +4,9 @@ Sec. 2.2 tunes two parameters of the K20 kernel (accumulators per thread and
 threads per block) by sweeping them on the target device.  The tunables
 here are the gfx950 kernel's compiled tile variants -- (MT row tiles per
 wave step, NBT beam tiles per workgroup, NBP beam tiles per pass, KRES K
-chunks in registers) -- and the work-unit length (store groups per wave).
+chunks in registers; KRES -1 streams weights from device memory, -2 is the
+eight-wave streamed form) -- and the work-unit length (store groups per
+wave).
 Each candidate is timed with HIP events on the caller's inputs; the fastest
 is applied with ``bf_plan_set_tile`` and remembered in a JSON cache keyed by
 device and problem shape.  The tile never changes the results (same K
@@ -57,11 +59,12 @@ def sgw_options(plan, tile) -> list:
     G = 1 if I == 1 else 2 if I == 2 else 4 * ((I + 3) // 4)
     base = tile[0] // gcd(tile[0], G)
     sg_total = -(-(plan.T // I) // 16)
+    waves = 8 if tile[3] == -2 else 4   # waves sharing one work unit
     opts = []
     k = 1
     while True:
         s = base * k
-        if s * G > 1024 or (k > 1 and (s - base) * 4 >= sg_total):
+        if s * G > 1024 or (k > 1 and (s - base) * waves >= sg_total):
             break
         opts.append(s)
         k *= 2
@@ -77,7 +80,7 @@ def apply_cached(plan, batch: bool = False) -> Optional[tuple]:
 def lds_bytes(plan, tile) -> int:
     """Dynamic LDS a tile stages for this plan (its beam range's weight rows
     for all K; none when the weights are read from device memory)."""
-    if tile[3] < 0:
+    if tile[3] == -1:
         return 0
     es = 4 if plan.precision == 0 else 2
     kpad = -(-2 * plan.N // 64) * 64
