@@ -344,10 +344,13 @@ int bf_plan_destroy(bf_plan_t plan);
  * uneven N, C, B, T; Sec. 1 mentions partitioning an array into independent
  * phased sub-arrays) run in one persistent launch: a grid sized to the
  * device whose workgroups take work units from a device queue spanning all
- * sets.  All plans must share precision, input format and integration class
- * (I == 1, I == 2, or I >= 3) and have their weights set; up to 16 plans.  The batch
- * references the plans (they must outlive it) and owns a device queue
- * counter.
+ * sets.  In an FP16/BF16 batch with I == 1 or I % 4 == 0, the sets whose 2N
+ * exceeds 128 run in a second persistent launch of the eight-wave streamed
+ * form, queued first on the same stream (one launch per kernel form).  All
+ * plans must share precision, input format and integration class (I == 1,
+ * I == 2, or I >= 3) and have their weights set; up to 16 plans.  The batch
+ * references the plans (they must outlive it) and owns the device queue
+ * counters.
  * Errors: BF_ERR_INVALID_ARG, BF_ERR_UNSUPPORTED, BF_ERR_OOM, BF_ERR_HIP.
  */
 int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n_plans);
@@ -360,8 +363,8 @@ int bf_batch_tile_candidates(bf_plan_t plan, int32_t* tiles, int32_t max_tiles);
 
 /* x_dev[i], p_dev[i]: host arrays of device pointers, one per plan, same
  * layout and alignment rules as bf_run; no output may overlap any set's
- * voltages or another set's output (else BF_ERR_INVALID_ARG).  One launch on
- * `stream` (after a one-thread queue reset kernel).  Each set's output is
+ * voltages or another set's output (else BF_ERR_INVALID_ARG).  One launch per
+ * kernel form on `stream`, each after a one-thread queue reset kernel.  Each set's output is
  * bitwise identical to bf_run of that plan alone. */
 int bf_batch_run(bf_batch_t batch, const int8_t* const* x_dev, float* const* p_dev, void* stream);
 

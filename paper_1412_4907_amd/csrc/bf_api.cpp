@@ -957,13 +957,57 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
     Launch L;
     size_t lds = 0;
     Tile common{4, 1, 1, 0};
-    const int st = fill_sets(bt->plans.data(), n, x, out, kLdsMax, &L, &lds, &common);
+    // validates every set (pointers, state, no output overlapping any input
+    // or another output) and fills the four-wave table of all of them
+    int st = fill_sets(bt->plans.data(), n, x, out, kLdsMax, &L, &lds, &common);
     if (st != BF_OK) return st;
     L.queue = bt->queue;
     const bf_plan_s* p0 = bt->plans[0];
     const bool multi = p0->vec16;
-    int per_cu = lds <= 80 * 1024 ? 2 : 1;
     hipError_t e = hipSuccess;
+    // Sets whose K needs more than two 64-wide chunks run the eight-wave
+    // streamed form in a persistent launch of their own (FP16/BF16, I == 1
+    // or I % 4 == 0); the others share the four-wave persistent launch.
+    if (multi && p0->prec != BF_FP32 && (p0->mode == bf::kModeI1 || p0->mode == bf::kModeGen4)) {
+      std::vector<bf_plan_t> wp, rp;
+      std::vector<const int8_t*> wx, rx;
+      std::vector<float*> wo, ro;
+      for (int i = 0; i < n; ++i) {
+        bf_plan_s* p = bt->plans[i];
+        const bool wide = p->Kpad > 2 * bf::kChunk && tile_ok(*p, bf::wide_tiles().back()) &&
+                          lds_bytes(p->prec, p->Kpad, bf::wide_tiles().back().nbt) <= kLdsMax;
+        (wide ? wp : rp).push_back(p);
+        (wide ? wx : rx).push_back(x[i]);
+        (wide ? wo : ro).push_back(out[i]);
+      }
+      if (!wp.empty()) {
+        Launch LW;
+        size_t ldw = 0;
+        st = fill_sets(wp.data(), (int)wp.size(), wx.data(), wo.data(), kLdsMax, &LW, &ldw, &common,
+                       true);
+        if (st != BF_OK) return st;
+        LW.queue = bt->queue + 32;  // a counter of its own, 128 bytes past the first
+        int occ = 0;
+        e = bf::launch_beamform_multi(p0->prec, p0->mode, p0->in4, LW, nullptr, 0, ldw, s, &occ,
+                                      true);
+        if (e != hipSuccess) return from_hip(e);
+        int64_t gw = std::min<int64_t>(LW.total_units, (int64_t)p0->n_cu * std::max(1, occ));
+        e = bf::launch_queue_reset(LW.queue, s);
+        if (e == hipSuccess)
+          e = bf::launch_beamform_multi(p0->prec, p0->mode, p0->in4, LW, nullptr,
+                                        (int)std::max<int64_t>(1, gw), ldw, s, nullptr, true);
+        if (e != hipSuccess) return from_hip(e);
+        if (!rp.empty()) {
+          st = fill_sets(rp.data(), (int)rp.size(), rx.data(), ro.data(), kLdsMax, &L, &lds,
+                         &common);
+          if (st != BF_OK) return st;
+          L.queue = bt->queue;
+        } else {
+          L.total_units = 0;
+        }
+      }
+    }
+    int per_cu = lds <= 80 * 1024 ? 2 : 1;
     if (multi) {
       int occ = 0;
       e = bf::launch_beamform_multi(p0->prec, p0->mode, p0->in4, L, nullptr, 0, lds, s, &occ);
@@ -972,12 +1016,14 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
     }
     int64_t grid = std::min<int64_t>(L.total_units, (int64_t)p0->n_cu * per_cu);
     if (grid < 1) grid = 1;
-    e = bf::launch_queue_reset(bt->queue, s);
-    if (e == hipSuccess) {
-      e = multi ? bf::launch_beamform_multi(p0->prec, p0->mode, p0->in4, L, nullptr, (int)grid,
-                                            lds, s, nullptr)
-                : bf::launch_beamform(p0->prec, p0->mode, p0->vec16, p0->in4, common, L,
-                                      (int)grid, lds, s);
+    if (L.total_units > 0) {
+      e = bf::launch_queue_reset(bt->queue, s);
+      if (e == hipSuccess) {
+        e = multi ? bf::launch_beamform_multi(p0->prec, p0->mode, p0->in4, L, nullptr, (int)grid,
+                                              lds, s, nullptr)
+                  : bf::launch_beamform(p0->prec, p0->mode, p0->vec16, p0->in4, common, L,
+                                        (int)grid, lds, s);
+      }
     }
     for (int i = 0; i < n && e == hipSuccess; ++i) e = mark_used(bt->plans[i], s);
     if (e == hipSuccess) e = hipEventRecord(bt->last_use, s);
