@@ -931,7 +931,8 @@ int bf_batch_create(bf_batch_t* out, const bf_plan_t* plans, int32_t n) {
     bf_batch_s* bt = new bf_batch_s();
     bt->plans.assign(plans, plans + n);
     bt->device = plans[0]->device;
-    hipError_t e = dev_alloc(bt->device, (void**)&bt->queue, 256);
+    // queue counters of the two persistent launches (four- and eight-wave)
+    hipError_t e = dev_alloc(bt->device, (void**)&bt->queue, 2 * bf::kQueueInts * sizeof(int32_t));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->last_use, hipEventDisableTiming);
     if (e != hipSuccess) {
       (void)dev_release(bt->device, {}, {bt->queue});
@@ -986,7 +987,7 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
         st = fill_sets(wp.data(), (int)wp.size(), wx.data(), wo.data(), kLdsMax, &LW, &ldw, &common,
                        true);
         if (st != BF_OK) return st;
-        LW.queue = bt->queue + 32;  // a counter of its own, 128 bytes past the first
+        LW.queue = bt->queue + bf::kQueueInts;  // counters of its own
         int occ = 0;
         e = bf::launch_beamform_multi(p0->prec, p0->mode, p0->in4, LW, nullptr, 0, ldw, s, &occ,
                                       true);
@@ -1090,7 +1091,8 @@ int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, in
     hipError_t e = hipGetDevice(&t->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&t->n_cu, hipDeviceAttributeMultiprocessorCount,
                                                    t->device);
-    if (e == hipSuccess) e = dev_alloc(t->device, (void**)&t->queue, 256);
+    if (e == hipSuccess)
+      e = dev_alloc(t->device, (void**)&t->queue, bf::kQueueInts * sizeof(int32_t));
     if (e == hipSuccess) e = dev_alloc(t->device, (void**)&t->table, sizeof(Launch));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming);
     int occ = 0;

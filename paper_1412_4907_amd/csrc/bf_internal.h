@@ -38,7 +38,8 @@ struct Prob {
 struct Launch {
   Prob prob[kMaxProbs];
   int64_t total_units;
-  int32_t* queue;     // persistent mode: device counter (zeroed before launch); else null
+  int32_t* queue;     // persistent mode: kXcds device counters, kQueueStride apart
+                      // (zeroed before launch); else null
   int32_t nprob;
   int32_t xcd_remap;  // non-persistent mode: group consecutive units per XCD
 };

@@ -13,6 +13,9 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kWideWaves = 8;   // waves per workgroup of the eight-wave form
 constexpr int kWideThreads = 64 * kWideWaves;
 constexpr int kKresWide = -2;   // Tile::kres of the eight-wave streamed form
+constexpr int kXcds = 8;        // accelerator dies (XCDs), each with its own L2
+constexpr int kQueueStride = 16;  // int32 slots between the per-XCD queue counters
+constexpr int kQueueInts = kXcds * kQueueStride;  // one persistent launch's counters
 constexpr int kChunk = 64;      // real K elements (32 antennas) per chunk
 constexpr int kLdsPad = 16;     // bytes added to each LDS weight row
 

@@ -149,7 +149,9 @@ __global__ void __launch_bounds__(64) weights_raw_kernel(const double* __restric
   }
 }
 
-__global__ void queue_reset_kernel(int32_t* q) { *q = 0; }
+__global__ void queue_reset_kernel(int32_t* q) {
+  if (threadIdx.x < kXcds) q[threadIdx.x * kQueueStride] = 0;
+}
 
 // Copies a set table from the kernel arguments into device memory, one dword
 // per thread per step.
@@ -194,7 +196,7 @@ hipError_t launch_weights_raw(int prec, const double* wraw, int N, int C, int B,
 }
 
 hipError_t launch_queue_reset(int32_t* q, hipStream_t s) {
-  return launch(queue_reset_kernel, 1, 1, s, q);
+  return launch(queue_reset_kernel, 1, kXcds, s, q);
 }
 
 hipError_t launch_table_store(const Launch& L, Launch* dst, hipStream_t s) {
