@@ -338,6 +338,13 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
                       t.kres == tmp.tile.kres;
     tmp.tile = t;
     tmp.sgw = same ? tmp.sgw : std::max(base, tmp.sgw / base * base);
+    if (wide && !same) {
+      // the set's own store-group count per wave was chosen for a four-wave
+      // tile: cap it so that the channel's store groups still reach all
+      // eight waves of a unit (a short block has few groups per channel)
+      const int32_t cap = std::max(base, SG / bf::kWideWaves / base * base);
+      tmp.sgw = std::min(tmp.sgw, cap);
+    }
     L->prob[i] = make_prob(&tmp, x[i], out[i], begin);
     L->prob[i].variant = variant;
     begin += units_for(tmp, t, tmp.sgw);
@@ -347,6 +354,16 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
   L->nprob = n;
   L->total_units = begin;
   L->xcd_remap = 0;
+  // sets that beamform one voltage block (serving: every request reads the
+  // block of the ring slot): units go out channel by channel over all sets,
+  // so the sets' beam ranges of one channel meet its voltages in L2
+  bool shared = n > 1;
+  for (int i = 1; i < n && shared; ++i)
+    shared = x[i] == x[0] && plans[i]->C == plans[0]->C && plans[i]->T == plans[0]->T &&
+             plans[i]->N == plans[0]->N && plans[i]->in4 == plans[0]->in4;
+  int64_t per_chan = 0;
+  for (int i = 0; i < n; ++i) per_chan += (int64_t)L->prob[i].ntr * L->prob[i].nbr;
+  L->chan_units = shared && per_chan < ((int64_t)1 << 30) ? (int32_t)per_chan : 0;
   *lds_out = lds;
   return BF_OK;
 }

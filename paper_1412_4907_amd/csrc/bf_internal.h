@@ -42,6 +42,10 @@ struct Launch {
                       // (zeroed before launch); else null
   int32_t nprob;
   int32_t xcd_remap;  // non-persistent mode: group consecutive units per XCD
+  int32_t chan_units; // > 0: every set reads the same voltages (same block,
+                      // C and T); the eight-wave kernels' queues then hand
+                      // out all sets' units of one channel together,
+                      // chan_units of them
 };
 
 // Host-side launcher for one (precision, mode, vec16, input format, tile)

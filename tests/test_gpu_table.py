@@ -90,3 +90,64 @@ def test_table_rejects_mismatched_plans(gpu):
     assert e.value.status == bf.ERR_UNSUPPORTED
     table.destroy()
     plan.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_eight_wave_table_sets_sharing_one_block(gpu, prec):
+    """Sets that read one voltage block (the serving case) run the
+    eight-wave table kernel, whose queues then go channel by channel over
+    all sets; the block is short (8 store groups per channel), so each set's
+    store groups per wave are capped to reach all eight waves.  Each set's
+    output equals the set run alone, bit for bit, whether the sets share the
+    block or not; one set is checked against the oracle."""
+    import torch
+    print(f"eight-wave table, shared block, {prec}", flush=True)
+    N, C, T, I = 160, 9, 8192, 64  # K = 320: five chunks, eight-wave form
+    g = np.random.default_rng(47)
+    pos = synth.disc_positions(N, 150.0, g)
+    freqs = np.linspace(402e6, 414e6, C)
+    x = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
+    xd = torch.from_numpy(x).to(gpu)
+    x2 = torch.from_numpy(g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)).to(gpu)
+    beams = [75, 16, 130, 33]
+    plans, dirs, solo = [], [], []
+    for b in beams:
+        d = synth.random_dirs(b, g)
+        p = bf.Plan(N, C, b, T, I, precision=prec)
+        p.set_weights(pos, d, freqs)
+        plans.append(p)
+        dirs.append(d)
+    for xin, tag in ((xd, "shared"), (x2, "shared, other block")):
+        solo = []
+        for p, b in zip(plans, beams):
+            out = torch.empty((C, b, T // I), device=gpu)
+            p.run(xin, out)
+            solo.append(out)
+        torch.cuda.synchronize()
+        table = bf.Table(N, I, prec)
+        outs = [torch.full((C, b, T // I), float("nan"), device=gpu) for b in beams]
+        table.set(plans, [xin] * len(plans), outs)
+        table.run()
+        torch.cuda.synchronize()
+        for i in range(len(plans)):
+            assert torch.equal(outs[i], solo[i]), (tag, i)
+        table.destroy()
+    # sets on different blocks: the set-major queue order
+    table = bf.Table(N, I, prec)
+    xs = [xd, x2, xd, x2]
+    outs = [torch.full((C, b, T // I), float("nan"), device=gpu) for b in beams]
+    table.set(plans, xs, outs)
+    table.run()
+    torch.cuda.synchronize()
+    for i, (p, b) in enumerate(zip(plans, beams)):
+        ref = torch.empty((C, b, T // I), device=gpu)
+        p.run(xs[i], ref)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], ref), ("mixed blocks", i)
+    # one set against the oracle on two channels
+    ref = oracle.beamform(oracle.weights(pos, dirs[0], freqs[:2]), x[:2], I)
+    assert_parity(outs[0][:2].cpu().numpy(), ref, 2e-3 if prec == "fp16" else 1e-2,
+                  "eight-wave table set vs oracle")
+    table.destroy()
+    for p in plans:
+        p.destroy()
