@@ -30,6 +30,12 @@ PEAK_HBM_GBS = 8000.0
 DTYPE = {"fp32": "f32", "fp16": "f16 (f32 accumulate)", "bf16": "bf16 (f32 accumulate)"}
 
 
+def progress(msg: str) -> None:
+    """One line on stderr per finished phase (the JSON result stays the only
+    line on stdout), so a long default run shows that it is alive."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,7 +244,7 @@ def load_traffic(kernel_key: str):
     return e.get("bytes_per_launch")
 
 
-def serve_bench(a, torch, dev):
+def serve_bench(a, torch, dev, emit=True):
     """Serving form: 256-antenna 16x16 array, blocks of 1024 channels x 8192
     samples (524.288 ms each), FP16, I=64, seeded Poisson beam-set requests
     (64..2048 beams, mean ~512 concurrently active) admitted by HBM footprint,
@@ -300,6 +306,7 @@ def serve_bench(a, torch, dev):
 
     reqs_spec = synth.serve_requests(64)
     out["throughput"] = run(reqs_spec, a.blocks)
+    progress(f"serve throughput: real-time factor {out['throughput']['rtf']}")
     out["paced"] = run(reqs_spec, a.blocks, arrivals=synth.serve_block_arrivals(a.blocks, period,
                                                                                  a.pace))
     host = []
@@ -307,7 +314,9 @@ def serve_bench(a, torch, dev):
         h = torch.empty(r.shape, dtype=r.dtype, pin_memory=True)
         h.copy_(r)
         host.append(h)
+    progress(f"serve paced: p99 {out['paced']['p99_block_ms']} ms")
     out["h2d"] = run(reqs_spec, min(a.blocks, 60), host_blocks=host)
+    progress(f"serve PCIe-fed: real-time factor {out['h2d']['rtf']}")
     del host
     curve = []
     for load in (128, 256, 512, 1024, 2048):
@@ -323,7 +332,9 @@ def serve_bench(a, torch, dev):
     out["p99_block_ms"] = out["paced"]["p99_block_ms"]
     out["block_period_ms"] = round(period * 1e3, 3)
     out["input_gen_s"] = round(gen_s, 1)
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def tracking_bench(a, torch, dev):
@@ -397,7 +408,7 @@ def tracking_bench(a, torch, dev):
     print(json.dumps(out), flush=True)
 
 
-def batch_bench(a, torch, dev):
+def batch_bench(a, torch, dev, emit=True):
     """Batching form: the 12 seeded beam sets of uneven N, C, B, T in one
     persistent launch (tiles from the autotuner cache or each set's default)."""
     from paper_1412_4907_amd import bf, synth, tune
@@ -458,7 +469,9 @@ def batch_bench(a, torch, dev):
     batch.destroy()
     for p in plans:
         p.destroy()
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -528,6 +541,7 @@ def main():
         return per, total, info
 
     per, total, info = leg(a.precision, a.steps, a.warmup)
+    progress(f"{w.name} {a.precision}: {total / a.steps:.3f} ms per block")
     ms = total / a.steps
     flops = w.flops
     value = flops / (ms * 1e-3) / 1e12
@@ -578,6 +592,7 @@ def main():
                 continue
             per2, total2, _ = leg(prec, a.steps, a.warmup)
             ms2 = total2 / a.steps
+            progress(f"{w.name} {prec}: {ms2:.3f} ms per block")
             v2 = flops / (ms2 * 1e-3) / 1e12
             ab2 = algorithmic_bytes(w, prec, a.output)
             extra[prec] = {"tflops": round(v2, 3), "ms_per_step": round(ms2, 4),
@@ -588,7 +603,31 @@ def main():
     del xd
     if not a.no_extra:
         out["precision_forms"] = precision_report(torch, dev)
+        progress("precision forms against the oracle")
+    if not a.no_extra and a.workload == "paper" and w.input_bits == 8 and a.output == "power":
+        # the batching and serving forms, in FP16 at their own workloads, so
+        # that the default run also records them (summaries of
+        # --workload batch / --workload serve)
+        import argparse
+        sub = argparse.Namespace(**vars(a))
+        sub.precision = "fp16"
+        b = batch_bench(sub, torch, dev, emit=False)
+        progress(f"batch fp16: {b['ms_per_step']} ms per batch")
+        sv = serve_bench(sub, torch, dev, emit=False)
+        progress(f"serve fp16: real-time factor {sv['real_time_factor']}")
+        out["other_workloads"] = {
+            "batch_fp16": {"workload": b["config"]["workload"], "ms_per_step": b["ms_per_step"],
+                           "tflops": b["value"], "roofline_frac": b["roofline_frac"],
+                           "sum_of_solo_ms": b["sum_of_solo_ms"]},
+            "serve_fp16": {"workload": sv["config"]["workload"], "tflops": sv["value"],
+                           "real_time_factor": sv["real_time_factor"],
+                           "mean_active_beams": sv["throughput"]["mean_active_beams"],
+                           "deadline_misses": sv["throughput"]["deadline_misses"],
+                           "paced_p50_block_ms": sv["p50_block_ms"],
+                           "paced_p99_block_ms": sv["p99_block_ms"],
+                           "blocks": sv["throughput"]["blocks"]}}
     if not a.no_cpu_baseline:
+        progress("CPU baseline (FP64 oracle)")
         cb = cpu_baseline(w, a.cpu_seconds)
         out["cpu_baseline"] = cb
         out["gpu_over_cpu"] = round(value / cb["value"], 1)
