@@ -343,10 +343,14 @@ int bf_plan_destroy(bf_plan_t plan);
  * Batching form: several independent plans (sub-arrays or beam sets of
  * uneven N, C, B, T; Sec. 1 mentions partitioning an array into independent
  * phased sub-arrays) run in one persistent launch: a grid sized to the
- * device whose workgroups take work units from a device queue spanning all
- * sets.  In an FP16/BF16 batch with I == 1 or I % 4 == 0, the sets whose 2N
- * exceeds 128 run in a second persistent launch of the eight-wave streamed
- * form, queued first on the same stream (one launch per kernel form).  All
+ * device whose workgroups take work units from device queues spanning all
+ * sets (one queue counter per XCD; a workgroup drains its own XCD's queue,
+ * which holds the channels c with c % 8 == XCD index, then helps the
+ * others).  In an FP16/BF16 batch with I == 1 or I % 4 == 0, the sets whose
+ * 2N exceeds 128 run in a second persistent launch of the eight-wave
+ * streamed form, queued first on the same stream (one launch per kernel
+ * form); when all of those sets read one voltage block, its queues hand out
+ * their units channel by channel over the sets.  All
  * plans must share precision, input format and integration class (I == 1,
  * I == 2, or I >= 3) and have their weights set; up to 16 plans.  The batch
  * references the plans (they must outlive it) and owns the device queue
@@ -384,9 +388,14 @@ int bf_batch_destroy(bf_batch_t batch);
  *
  * bf_table_create: for plans with n_antennas antennas, integration I, the
  * given precision and input format (flags: 0 or BF_INPUT_4BIT; 2 n_antennas
- * must be a multiple of 16) on the current device.  It fixes the launch: dynamic LDS of the largest batching variant
- * that keeps two workgroups per CU, grid = CUs x workgroups per CU.  Owns a
- * device table (a few KB) and a queue counter.
+ * must be a multiple of 16) on the current device.  It fixes the launch:
+ * for FP16/BF16 with I == 1 or I % 4 == 0 and 2N > 128 the eight-wave
+ * streamed kernel (dynamic LDS of its widest beam range, one workgroup per
+ * CU; sets that read one voltage block, as in serving, are handed out
+ * channel by channel), else the four-wave kernel with the dynamic LDS of the
+ * largest batching variant that keeps two workgroups per CU; grid = CUs x
+ * workgroups per CU.  Owns a device table (a few KB) and the per-XCD queue
+ * counters.
  * Errors: BF_ERR_INVALID_ARG, BF_ERR_UNSUPPORTED, BF_ERR_OOM, BF_ERR_HIP.
  */
 int bf_table_create(bf_table_t* out, int32_t n_antennas, int32_t integration, int32_t precision,
