@@ -13,11 +13,13 @@ builds those ideas on one MI355X:
   memory on a copy stream, the PCIe-bound variant);
 * beam-set requests (a set of pointings, a lifetime in blocks) arrive at any
   time; at each block boundary the scheduler retires finished requests and
-  admits waiting ones while their HBM footprint (weights + double-buffered
-  output) fits the budget -- requests arriving while others run join the
+  admits waiting ones while their HBM footprint (weights + one output
+  buffer per ring slot) fits the budget -- requests arriving while others run join the
   next block's launch (continuous batching, not a queue of whole jobs);
 * each admitted request owns a plan (weights generated on the device once,
-  at admission) and two output buffers; integration state never leaves HBM;
+  at admission) and one output buffer per ring slot (block k writes buffer
+  k mod slots, so a block's output stays intact while the later blocks that
+  can be in flight run); integration state never leaves HBM;
 * the per-block work -- one queue-reset kernel and one persistent beamform
   launch over every active request -- reads its set table (which requests,
   which ring slot, which output buffers) from device memory, so it is
@@ -210,6 +212,10 @@ class GpuExecutor:
         self.precision = precision
         self.input_bits = input_bits     # 8: int8 [C][T][N][2] blocks; 4: packed uint8 [C][T][N]
         self.ring = list(ring)           # device voltage blocks
+        # output buffers per request: one per block that can be in flight
+        # (a block's output is written while up to len(ring) - 1 later
+        # blocks are queued behind it)
+        self.n_out = max(2, len(self.ring))
         self.use_graphs = use_graphs
         self.stream = torch.cuda.Stream()
         # PCIe-fed variant: every block is first copied from pinned host memory
@@ -240,7 +246,7 @@ class GpuExecutor:
             plan.set_weights(self.pos, r.dirs, self.freqs, stream=self.stream)
             self.outs[r.rid] = [torch.empty((self.C, r.n_beams, self.T // self.I),
                                             dtype=torch.float32, device="cuda")
-                                for _ in range(2)]
+                                for _ in range(self.n_out)]
         # the table kernel's own tuned tile for this shape (B bucketed), if
         # the tile cache has one; else the plan keeps its creation tile
         if plan.apply_tuned(batch=True):
@@ -271,9 +277,10 @@ class GpuExecutor:
                 keep.append((ev, p, outs))
         self.retiring = keep
 
-    def run_block(self, ids: Sequence[int], slot: int, parity: int):
-        """Enqueue one block's work on the serve stream; returns an event
-        recorded after it."""
+    def run_block(self, ids: Sequence[int], slot: int, out_slot: int):
+        """Enqueue one block's work on the serve stream (voltages from ring
+        slot ``slot``, each request's output into its buffer ``out_slot``);
+        returns an event recorded after it."""
         torch = self.torch
         ids = tuple(sorted(ids))
         if self.host_blocks is not None:
@@ -288,7 +295,7 @@ class GpuExecutor:
             self.h2d_bytes += self.ring[slot].numel()
         if ids:
             self.table.set([self.plans[i] for i in ids], [self.ring[slot]] * len(ids),
-                           [self.outs[i][parity] for i in ids], stream=self.stream)
+                           [self.outs[i][out_slot] for i in ids], stream=self.stream)
             if self.graph is None or not self.use_graphs:
                 # first block: run eagerly (also the warm-up that keeps
                 # one-time runtime calls out of the capture), then capture
@@ -311,8 +318,8 @@ class GpuExecutor:
             self.last_use[i] = ev
         return ev
 
-    def output(self, rid: int, parity: int):
-        return self.outs[rid][parity]
+    def output(self, rid: int, out_slot: int):
+        return self.outs[rid][out_slot]
 
     def close(self) -> None:
         self.stream.synchronize()
@@ -340,6 +347,7 @@ def serve(executor, scheduler: Scheduler, requests: Sequence[Request], n_blocks:
     records: List[BlockRecord] = []
     inflight = []  # (event, record)
     n_slots = max(1, len(getattr(executor, "ring", [None])))
+    n_out = max(2, getattr(executor, "n_out", 2))
     t0 = time.perf_counter()
     watcher = CompletionWatcher(t0)
     for k in range(n_blocks):
@@ -371,7 +379,7 @@ def serve(executor, scheduler: Scheduler, requests: Sequence[Request], n_blocks:
         arrived = release if release is not None else time.perf_counter() - t0
         rec = BlockRecord(k, sorted(scheduler.active), sum(r.n_beams for r in scheduler.active.values()),
                           arrived)
-        ev = executor.run_block(rec.active, k % n_slots, k & 1)
+        ev = executor.run_block(rec.active, k % n_slots, k % n_out)
         watcher.add(ev, rec)
         inflight.append((ev, rec))
         records.append(rec)

@@ -224,3 +224,39 @@ def test_summarize_deadline_from_records():
     st = serve.summarize(recs, 0.1, deadline_s=0.25)
     assert st["deadline_misses"] == 1
     assert st["p50_block_ms"] == pytest.approx(125.0)
+
+
+class RingExecutor(TimedExecutor):
+    """TimedExecutor with a ring of `slots` voltage slots and as many output
+    buffers per request; records which slot and output buffer each block used
+    and how many blocks were in flight when it was enqueued."""
+
+    def __init__(self, work_s, slots):
+        super().__init__(work_s)
+        self.ring = [None] * slots
+        self.n_out = slots
+        self.used = []
+        self.events = []
+
+    def run_block(self, ids, slot, out_slot):
+        now = time.perf_counter()
+        in_flight = sum(1 for e in self.events if e.done_at > now)
+        self.used.append((slot, out_slot, in_flight))
+        ev = super().run_block(ids, slot, out_slot)
+        self.events.append(ev)
+        return ev
+
+
+@pytest.mark.parametrize("slots", [2, 3])
+def test_ring_slots_bound_blocks_in_flight_and_output_buffers(slots):
+    """Block k reads ring slot k % slots and writes each request's output
+    buffer k % slots; blocks released at once never have more than `slots`
+    in flight (the host waits for block k - slots before enqueuing block k),
+    so no block overwrites a slot or an output buffer still in use."""
+    ex = RingExecutor([0.01] * 9, slots)
+    sch = serve.Scheduler(1 << 30, lambda r: 1)
+    reqs = [serve.Request(0, np.zeros((4, 3)), lifetime=None)]
+    serve.serve(ex, sch, reqs, n_blocks=9, block_period_s=0.5)
+    assert [(s, o) for s, o, _ in ex.used] == [(k % slots, k % slots) for k in range(9)]
+    assert max(n for _, _, n in ex.used) <= slots - 1
+    assert max(n for _, _, n in ex.used) == slots - 1  # the ring is used in full
