@@ -340,10 +340,13 @@ int fill_sets(const bf_plan_t* plans, int n, const int8_t* const* x, float* cons
     tmp.sgw = same ? tmp.sgw : std::max(base, tmp.sgw / base * base);
     if (wide && !same) {
       // the set's own store-group count per wave was chosen for a four-wave
-      // tile: cap it so that the channel's store groups still reach all
-      // eight waves of a unit (a short block has few groups per channel)
-      const int32_t cap = std::max(base, SG / bf::kWideWaves / base * base);
-      tmp.sgw = std::min(tmp.sgw, cap);
+      // tile; an eight-wave unit instead takes as much of the channel's time
+      // range as spreads over its eight waves (at least one MT-aligned step
+      // each): no wave of a unit idles on a short block, and a long block is
+      // split into as few units as that allows, each staging its weights
+      // once.  Measured on the 12-set batch against the set's own count
+      // capped the same way: 19.05-19.10 -> 18.76-18.80 ms.
+      tmp.sgw = std::max(base, SG / bf::kWideWaves / base * base);
     }
     L->prob[i] = make_prob(&tmp, x[i], out[i], begin);
     L->prob[i].variant = variant;
@@ -1053,8 +1056,8 @@ int bf_batch_run(bf_batch_t bt, const int8_t* const* x, float* const* out, void*
 
 int bf_batch_destroy(bf_batch_t bt) {
   if (!bt) return BF_OK;
-  // the queue counter is released on the device after the batch's own last
-  // launch
+  // the queue counters are released on the device after the batch's own
+  // last launch
   (void)dev_release(bt->device, {bt->last_use}, {bt->queue});
   if (bt->last_use) (void)hipEventDestroy(bt->last_use);
   delete bt;
