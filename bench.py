@@ -54,7 +54,7 @@ def parse():
                          "(Poisson block arrivals with mean gap block_period / pace)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the other-precision legs")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--retune", action="store_true", help="re-run the autotuner")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0,
                     help="serve: HBM budget for admitted requests")
