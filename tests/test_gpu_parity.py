@@ -149,9 +149,10 @@ def test_ragged_shapes(gpu, shape, prec):
     assert_parity(got, ref, TOL[prec], f"{shape} {prec}")
 
 
-# --- register-resident pipelined form (FP16/BF16) -------------------------------
+# --- register-resident pipelined form ------------------------------------------
 # Shapes the pipelined unit form serves (2N a multiple of 16, every K chunk in
-# registers, I == 1 or a multiple of the row-tile count, T/I a multiple of 4),
+# registers, I == 1 or a multiple of the row-tile count, T/I a multiple of 4;
+# FP32 with one beam tile per pass and 2N <= 64),
 # with beam counts that leave a partial last beam range, so pipelined and
 # general units share one launch.  Checked against the oracle, and bit for bit
 # against a streaming tile, which never takes the pipelined form (both sum each
@@ -164,7 +165,7 @@ FAST = [  # N, C, B, T, I
 ]
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("shape", FAST, ids=[f"N{s[0]}C{s[1]}B{s[2]}T{s[3]}I{s[4]}" for s in FAST])
 def test_pipelined_form(gpu, shape, prec):
     N, C, B, T, I = shape
@@ -174,7 +175,10 @@ def test_pipelined_form(gpu, shape, prec):
     dirs = synth.random_dirs(B, g)
     freqs = np.linspace(401e6, 415e6, C)
     x = g.integers(-128, 128, (C, T, N, 2)).astype(np.int8)
-    resident = (4, 8, 1, 1 if 2 * N <= 64 else 2, 4)
+    if prec == "fp32":
+        resident = (4, 4, 1, 1, 4) if 2 * N <= 64 else (4, 8, 1, 2, 4)
+    else:
+        resident = (4, 8, 1, 1 if 2 * N <= 64 else 2, 4)
     with bf.Plan(N, C, B, T, I, precision=prec) as plan:
         plan.set_weights(pos, dirs, freqs)
         plan.set_tile(*resident)
